@@ -1,0 +1,160 @@
+"""ctypes front of ``cplbm_oracle.c`` (test infrastructure only).
+
+Every function here marshals numpy arrays and forwards to the C oracle; the
+arithmetic lives in the C file, which cites the paper for each step.
+"""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cplbm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+EOS_VDW, EOS_RK, EOS_RKS, EOS_PR, EOS_CS = 0, 1, 2, 3, 4
+
+
+class OracleParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("bc_y", C.c_int32), ("eos", C.c_int32),
+        ("wall_ux", C.c_double), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
+        ("T", C.c_double), ("alpha_T", C.c_double), ("kappa", C.c_double),
+        ("tau", C.c_double), ("k", C.c_double), ("mu_cap", C.c_double),
+        ("cfd_alpha", C.c_double),
+    ]
+
+
+def build(force=False):
+    """Compile the oracle with gcc (IEEE order, no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(LIB)
+        d, i32, i64, P = C.c_double, C.c_int, C.c_int64, C.c_void_p
+        pp = C.POINTER(OracleParams)
+        for name, res, args in [
+            ("orc_alpha_T", d, [i32, d, d, d]),
+            ("orc_p0", d, [i32, d, d, d, d, d, d]),
+            ("orc_mu0", d, [i32, d, d, d, d, d, d]),
+            ("orc_mu0_capped", d, [pp, d]),
+            ("orc_cfm_line", None, [i32, d, P, P]),
+            ("orc_feq", d, [i32, d, d, d]),
+            ("orc_node_moments", None, [P, P, P, P]),
+            ("orc_collide_node", None, [P, d, d, d, d, d, d, P]),
+            ("orc_stream", None, [pp, P, P, P]),
+            ("orc_init", None, [pp, P, P, P, P]),
+            ("orc_step", None, [pp, P]),
+            ("orc_run", None, [pp, P, i64]),
+            ("orc_moments", None, [pp, P, P, P, P, P, P, P]),
+            ("orc_run_until_converged", i32, [pp, P, d, i64, i64, C.POINTER(i64),
+                                              C.POINTER(d)]),
+        ]:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _nullable(a):
+    return None if a is None else _ptr(a)
+
+
+def alpha_T(eos, T, Tc, omega):
+    return load().orc_alpha_T(eos, T, Tc, omega)
+
+
+def p0(eos, a, b, R, T, al, rho):
+    f = load().orc_p0
+    return np.vectorize(lambda r: f(eos, a, b, R, T, al, float(r)))(rho)
+
+
+def mu0(eos, a, b, R, T, al, rho):
+    f = load().orc_mu0
+    return np.vectorize(lambda r: f(eos, a, b, R, T, al, float(r)))(rho)
+
+
+def mu0_capped(p, rho):
+    f = load().orc_mu0_capped
+    return np.vectorize(lambda r: f(C.byref(p), float(r)))(rho)
+
+
+def cfm_line(u, alpha):
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    d = np.empty_like(u)
+    load().orc_cfm_line(len(u), alpha, _ptr(u), _ptr(d))
+    return d
+
+
+def feq(i, rho, ux, uy):
+    return load().orc_feq(i, rho, ux, uy)
+
+
+def collide_node(fi, rho, ux, uy, Fx, Fy, tau):
+    fi = np.ascontiguousarray(fi, dtype=np.float64)
+    out = np.empty(9)
+    load().orc_collide_node(_ptr(fi), rho, ux, uy, Fx, Fy, tau, _ptr(out))
+    return out
+
+
+def stream(p, fstar, rho):
+    fstar = np.ascontiguousarray(fstar, dtype=np.float64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    out = np.full_like(fstar, np.nan)
+    load().orc_stream(C.byref(p), _ptr(fstar), _ptr(rho), _ptr(out))
+    return out
+
+
+def init(p, rho0, ux0, uy0):
+    f = np.empty((9, p.ny, p.nx))
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho0, ux0, uy0)]
+    load().orc_init(C.byref(p), *[_ptr(a) for a in args], _ptr(f))
+    return f
+
+
+def step(p, f):
+    load().orc_step(C.byref(p), _ptr(f))
+    return f
+
+
+def run(p, f, nsteps):
+    load().orc_run(C.byref(p), _ptr(f), int(nsteps))
+    return f
+
+
+def moments(p, f, want_force=False):
+    """rho, v = u + F/(2 rho), and (optionally) mu, Fx, Fy of the state f."""
+    sh = (p.ny, p.nx)
+    rho, vx, vy, mu, fx, fy = (np.empty(sh) for _ in range(6))
+    load().orc_moments(C.byref(p), _ptr(f), _ptr(rho), _ptr(vx), _ptr(vy),
+                       _ptr(mu), _ptr(fx), _ptr(fy))
+    if want_force:
+        return rho, vx, vy, mu, fx, fy
+    return rho, vx, vy
+
+
+def run_until_converged(p, f, tol, every, max_steps):
+    steps = C.c_int64(0)
+    delta = C.c_double(0.0)
+    st = load().orc_run_until_converged(C.byref(p), _ptr(f), tol, int(every), int(max_steps),
+                                        C.byref(steps), C.byref(delta))
+    return st, steps.value, delta.value

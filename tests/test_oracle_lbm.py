@@ -1,0 +1,214 @@
+"""Pins of the oracle's lattice Boltzmann scheme (Sec. 2 and Sec. 5 of the
+paper): exact lattice identities, conservation, symmetry, and the
+equilibrium properties the paper reports."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analytic as A
+from paper_1906_09530_amd import inputs
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+
+
+def test_lattice_is_the_printed_d2q9(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "paper_printed.json")))["d2q9"]
+    w = np.array([a / b for a, b in g["weights"]])
+    e = np.array(g["velocities"])
+    np.testing.assert_array_equal(e[:, 0], EX)
+    np.testing.assert_array_equal(e[:, 1], EY)
+    # the oracle's feq at rest is w_i rho
+    np.testing.assert_allclose([oracle.feq(i, 2.0, 0.0, 0.0) for i in range(9)], 2.0 * w,
+                               rtol=1e-15)
+
+
+@pytest.mark.parametrize("rho,ux,uy", [(1.0, 0.0, 0.0), (0.37, 0.11, -0.07), (9.2, -0.2, 0.15)])
+def test_equilibrium_moments(rho, ux, uy):
+    """Eq. 2 on D2Q9: zeroth, first and second moments are rho, rho u and
+    rho u u + c_s^2 rho I exactly (up to round-off)."""
+    f = np.array([oracle.feq(i, rho, ux, uy) for i in range(9)])
+    assert f.sum() == pytest.approx(rho, rel=1e-15)
+    assert (EX * f).sum() == pytest.approx(rho * ux, abs=1e-15 * rho)
+    assert (EY * f).sum() == pytest.approx(rho * uy, abs=1e-15 * rho)
+    assert (EX * EX * f).sum() == pytest.approx(rho * ux * ux + rho / 3, rel=1e-14)
+    assert (EY * EY * f).sum() == pytest.approx(rho * uy * uy + rho / 3, rel=1e-14)
+    assert (EX * EY * f).sum() == pytest.approx(rho * ux * uy, abs=1e-14 * rho)
+
+
+def test_exact_difference_forcing_moments():
+    """Eqs. 1 and 5: BGK conserves mass and momentum; the exact-difference
+    term adds the momentum F and no mass."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        fi = rng.uniform(0.01, 0.3, 9)
+        rho = fi.sum()
+        jx = (EX * fi).sum()
+        jy = (EY * fi).sum()
+        Fx, Fy = rng.normal(0, 0.01, 2)
+        tau = rng.uniform(0.55, 3.0)
+        fo = oracle.collide_node(fi, rho, jx / rho, jy / rho, Fx, Fy, tau)
+        assert fo.sum() == pytest.approx(rho, rel=1e-14)
+        assert (EX * fo).sum() == pytest.approx(jx + Fx, abs=1e-15)
+        assert (EY * fo).sum() == pytest.approx(jy + Fy, abs=1e-15)
+        # tau = 1 with no force relaxes straight to equilibrium
+        f1 = oracle.collide_node(fi, rho, jx / rho, jy / rho, 0.0, 0.0, 1.0)
+        np.testing.assert_allclose(f1, [oracle.feq(i, rho, jx / rho, jy / rho) for i in range(9)],
+                                   rtol=1e-14)
+
+
+def test_streaming_is_a_permutation():
+    """Streaming (left side of Eq. 1) moves population i by e_i, bit for bit,
+    on a periodic lattice."""
+    p = A.params(A.EOS_CS, 0.7, 7, 5, kappa=0.0, tau=1.0, k=1.0)
+    fs = np.random.default_rng(2).standard_normal((9, 5, 7))
+    out = oracle.stream(p, fs, np.ones((5, 7)))
+    for i in range(9):
+        np.testing.assert_array_equal(out[i], np.roll(fs[i], (EY[i], EX[i]), axis=(0, 1)))
+
+
+def test_bounce_back_walls():
+    """Half-way bounce-back between walls: a population leaving the fluid
+    returns to its own node reversed, a moving wall adding
+    -2 w_i rho (e_i . U)/c_s^2; interior populations stream normally."""
+    U = 0.03
+    p = A.params(A.EOS_CS, 0.7, 6, 4, kappa=0.0, tau=1.0, k=1.0, bc_y=1, wall_ux=U)
+    fs = np.random.default_rng(5).standard_normal((9, 4, 6))
+    rho = np.random.default_rng(6).uniform(0.1, 0.5, (4, 6))
+    out = oracle.stream(p, fs, rho)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    opp = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+    for i in range(9):
+        for y in range(4):
+            for x in range(6):
+                ty = y + EY[i]
+                if 0 <= ty < 4:
+                    assert out[i, ty, (x + EX[i]) % 6] == fs[i, y, x]
+                else:
+                    exp = fs[i, y, x] - 2 * w[i] * rho[y, x] * EX[i] * U * 3
+                    assert out[opp[i], y, x] == pytest.approx(exp, rel=1e-15, abs=1e-15)
+    assert not np.isnan(out).any()
+
+
+def _cs_drop(n, T_r=0.7, kappa=0.0, k=1.0, tau=1.0, alpha=0.25, R=None, W=4.0, noise=0.0,
+             seed=0, **kw):
+    e = A.EOS(A.EOS_CS)
+    g, l = (float(v) for v in e.maxwell(T_r))
+    p = A.params(A.EOS_CS, T_r, n, n, kappa=kappa, tau=tau, k=k, cfd_alpha=alpha, **kw)
+    rho, ux, uy = inputs.droplet(n, n, g, l, n / 4 if R is None else R, W, seed=seed,
+                                 noise=noise)
+    return p, oracle.init(p, rho, ux, uy)
+
+
+def test_mass_conservation_periodic():
+    """Total mass is conserved to round-off (Eqs. 1 and 5 conserve it node
+    by node; streaming permutes it)."""
+    p, f = _cs_drop(32, kappa=0.1, k=0.2, alpha=1 / 3, W=6.0, noise=1e-6)
+    m0 = f.sum()
+    oracle.run(p, f, 300)
+    assert abs(f.sum() / m0 - 1) < 1e-13
+
+
+def test_mass_conservation_moving_walls():
+    """Half-way bounce-back conserves mass, also with tangentially moving
+    walls (the wall term is odd in e_x and sums to zero)."""
+    e = A.EOS(A.EOS_CS)
+    g, l = (float(v) for v in e.maxwell(0.6))
+    p = A.params(A.EOS_CS, 0.6, 48, 40, kappa=0.1, tau=0.8, k=0.2, bc_y=1, wall_ux=0.02)
+    rho, ux, uy = inputs.splash(48, 40, g, l, radius=8, width=4.0, film=8,
+                                drop_center=(24, 24), drop_uy=-0.02, frame_ux=0.02)
+    f = oracle.init(p, rho, ux, uy)
+    m0 = f.sum()
+    oracle.run(p, f, 200)
+    assert np.isfinite(f).all()
+    assert abs(f.sum() / m0 - 1) < 1e-13
+
+
+def test_flat_interface_keeps_zero_tangential_velocity_bitwise():
+    """A slab uniform in x stays uniform: u_x and v_x are exactly zero."""
+    e = A.EOS(A.EOS_CS)
+    g, l = (float(v) for v in e.maxwell(0.7))
+    p = A.params(A.EOS_CS, 0.7, 8, 64, kappa=0.1, tau=1.0, k=0.2)
+    rho, ux, uy = inputs.slab(8, 64, g, l, 4.0)
+    f = oracle.init(p, rho, ux, uy)
+    oracle.run(p, f, 200)
+    r, vx, vy = oracle.moments(p, f)
+    np.testing.assert_array_equal(vx, 0.0)
+    assert (r == r[:, :1]).all()
+    assert np.abs(vy).max() > 0
+
+
+def test_drop_keeps_d4_symmetry():
+    """A drop centred at (n/2, n/2) keeps the mirror symmetries x -> n - x,
+    y -> n - y and the diagonal symmetry x <-> y of the square lattice."""
+    n = 32
+    p, f = _cs_drop(n, kappa=0.1, k=0.2, alpha=1 / 3, W=6.0)
+    oracle.run(p, f, 150)
+    r, vx, vy = oracle.moments(p, f)
+    mirror = np.roll(r[:, ::-1], 1, axis=1)       # x -> n - x (mod n)
+    assert np.abs(r - mirror).max() < 1e-12 * r.max()
+    assert np.abs(r - r.T).max() < 1e-12 * r.max()
+    assert np.abs(vx - vy.T).max() < 1e-12
+
+
+def test_mu_cap_only_binds_outside_the_liquid_range():
+    """Sec. 5.6: a limit far above the bulk chemical potentials changes
+    nothing (bit for bit); a node pushed to rho >= 1/b blows up without the
+    limit and stays finite with it."""
+    e = A.EOS(A.EOS_PR)
+    g, l = (float(v) for v in e.maxwell(0.6))
+    kw = dict(kappa=0.002, tau=1.0, k=0.1)
+    p_off = A.params(A.EOS_PR, 0.6, 24, 24, **kw)
+    p_far = A.params(A.EOS_PR, 0.6, 24, 24, mu_cap=1e6, **kw)
+    rho, ux, uy = inputs.droplet(24, 24, g, l, 7, 5.0)
+    f1 = oracle.init(p_off, rho, ux, uy)
+    f2 = f1.copy()
+    oracle.run(p_off, f1, 50)
+    oracle.run(p_far, f2, 50)
+    np.testing.assert_array_equal(f1, f2)
+
+    rho_bad = rho.copy()
+    rho_bad[12, 12] = 10.6                             # beyond 1/b = 10.5
+    p_cap = A.params(A.EOS_PR, 0.6, 24, 24, mu_cap=6.0, **kw)
+    fb = oracle.init(p_off, rho_bad, ux, uy)
+    oracle.run(p_off, fb, 1)
+    assert not np.isfinite(fb).all()
+    fc = oracle.init(p_cap, rho_bad, ux, uy)
+    oracle.run(p_cap, fc, 20)
+    assert np.isfinite(fc).all()
+
+
+def _converged_slab(T_r, kappa, k, tau, ny=128):
+    e = A.EOS(A.EOS_CS)
+    g, l = (float(v) for v in e.maxwell(T_r))
+    p = A.params(A.EOS_CS, T_r, 4, ny, kappa=kappa, tau=tau, k=k)
+    rho, ux, uy = inputs.slab(4, ny, g, l, 4.0)
+    f = oracle.init(p, rho, ux, uy)
+    st, steps, d = oracle.run_until_converged(p, f, 1e-12, 100, 300000)
+    assert st == 0
+    r, vx, vy, mu, fx, fy = oracle.moments(p, f, want_force=True)
+    return r[:, 0], mu[:, 0], g, l
+
+
+def test_flat_slab_coexistence_and_tau_independence():
+    """Sec. 5.1: coexistence densities of a flat slab against the Maxwell
+    construction, and their independence of the relaxation time (SRT at
+    tau = 0.8 and 3.0).  The liquid density lands within 1e-4 of Maxwell;
+    the gas density, whose interface tail is steepest in ln rho, within 1e-2
+    at this resolution (k = 0.2, a 5.5-node interface)."""
+    r1, mu1, g, l = _converged_slab(0.7, 0.1, 0.2, 0.8)
+    r2, mu2, _, _ = _converged_slab(0.7, 0.1, 0.2, 3.0)
+    ny = len(r1)
+    assert abs(r1[ny // 2] / l - 1) < 1e-4
+    assert abs(r1[0] / g - 1) < 1e-2
+    # tau independence of the equilibrium
+    np.testing.assert_allclose(r1, r2, rtol=1e-7)
+    # the chemical potential is uniform inside each bulk phase and waves
+    # only across the transition regions (Fig. 5 and its discussion)
+    wave = np.ptp(mu1)
+    assert np.ptp(mu1[ny // 2 - 8:ny // 2 + 8]) < 1e-4 * wave
+    # the gas core sits closer (in decay lengths) to the interfaces
+    assert np.ptp(np.concatenate([mu1[:8], mu1[-8:]])) < 1e-2 * wave
