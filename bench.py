@@ -1,0 +1,173 @@
+"""Benchmark of the solver's time step on one MI355X.
+
+Workload: a static drop in a 1024 x 1024 periodic D2Q9 FP64 mesh, Peng-Robinson
+EOS (a = 2/49, b = 2/21, R = 1, omega = 0.344) at T/T_c = 0.5, radius 200,
+tanh initial interface of width 10 between the Maxwell densities
+(Sec. 5.3, Eq. 41), tau = 0.8, upper limit of the chemical potential 6
+(Sec. 5.6), k = 0.1, kappa = 0.004, sixth-order compact scheme.
+
+One "step" is one lattice-Boltzmann time step of the whole mesh (the three
+kernels of the solver).  Prints one JSON line with MLUPS (whole job), the
+roofline entry of the dominant kernel (algorithmic bytes / its average
+duration, HIP events on the solver's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 20000] [--warmup 200]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (D2Q9 FP64) + % peak HBM BW; sweep/warm-start time-to-converge vs plain"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per node of each kernel (FP64):
+#   row pass A: read f (9 x 8), write rho and d2/dx2 rho (2 x 8)
+#   column pass B: read rho, d2/dx2 rho; write mu, F_y
+#   row pass C: read f, mu, F_y; write f (9 x 8)
+PASS_NAMES = ["rows_rho", "cols_mu", "rows_collide"]
+PASS_BYTES = [88, 32, 160]
+
+NX = NY = 1024
+CFG = dict(T_r=0.5, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0, radius=200.0, width=10.0)
+
+
+def workload_params(lbm):
+    return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
+                      k=CFG["k"], mu_cap=CFG["mu_cap"])
+
+
+def cpu_baseline(rho0, ux0, uy0, budget_s=15.0):
+    """The oracle on the host, single thread, on the first steps of the same
+    workload until about `budget_s` of CPU work."""
+    import oracle
+    from oracle import analytic as A
+    op = A.params(A.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"], k=CFG["k"],
+                  mu_cap=CFG["mu_cap"])
+    f = oracle.init(op, rho0, ux0, uy0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.step(op, f)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": NX * NY * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "first %d steps of the same 1024x1024 PR drop, single-threaded C oracle "
+                      "(%.1f s)" % (steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--pass-steps", type=int, default=1000,
+                    help="steps timed per kernel with HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver is a single-GPU build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1906_09530_amd import inputs, lbm
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    p = workload_params(lbm)
+    rho_g, rho_l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.droplet(NX, NY, rho_g, rho_l, CFG["radius"], CFG["width"])
+    d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+    s = lbm.Solver(p, *d, stream=stream.cuda_stream)
+
+    print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+
+    print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    done = 0
+    chunk = 2000
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        s.step(n)
+        done += n
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+    mlups = NX * NY / (ms_per_step * 1e-3) / 1e6
+
+    # per-kernel durations with HIP events on the solver's stream
+    print("per-kernel timing over %d steps" % args.pass_steps, file=sys.stderr, flush=True)
+    pass_ms = s.time_passes(args.pass_steps)
+    gbs = [PASS_BYTES[i] * NX * NY / (pass_ms[i] * 1e-3) / 1e9 for i in range(3)]
+    dom = int(np.argmax(pass_ms))
+
+    r, vx, vy = s.moments()
+    finite = bool(np.isfinite(r).all())
+    inside = r[NY // 2, NX // 2]
+    outside = r[0, 0]
+    steps_total = s.steps_taken
+    s.close()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, ux0, uy0)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "static PR drop, 1024x1024 periodic D2Q9, T/Tc=0.5, R=200, W=10, "
+                        "tau=0.8, mu limit 6, k=0.1, kappa=0.004, 6th-order compact FD",
+            "nx": NX, "ny": NY, "eos": "PR", "omega": 0.344, "T_r": CFG["T_r"],
+            "k": CFG["k"], "kappa": CFG["kappa"], "tau": CFG["tau"], "mu_cap": CFG["mu_cap"],
+            "radius": CFG["radius"], "width": CFG["width"],
+        },
+        "roofline": {
+            "kernel": PASS_NAMES[dom],
+            "bound": "hbm",
+            "achieved": round(gbs[dom], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(gbs[dom] / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_node": PASS_BYTES[dom],
+            "avg_ms": round(pass_ms[dom], 6),
+        },
+        "kernels": {PASS_NAMES[i]: {"avg_ms": round(pass_ms[i], 6), "GB_s": round(gbs[i], 1),
+                                    "bytes_per_node": PASS_BYTES[i]} for i in range(3)},
+        "step_algorithmic_GB_s": round(sum(PASS_BYTES) * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
+        "wall_s": round(wall, 3),
+        "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
+                  "rho_corner": float(outside), "max_speed": float(np.hypot(vx, vy).max()),
+                  "rho_g_maxwell": rho_g, "rho_l_maxwell": rho_l},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

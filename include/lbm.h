@@ -1,0 +1,176 @@
+/*
+ * lbm.h -- C ABI of libcplbm, the MI355X (gfx950) solver for the
+ * chemical-potential multiphase lattice Boltzmann method of Wen, Zhao, Qiu,
+ * Ye and Shan, "Chemical-Potential Multiphase Lattice Boltzmann Method with
+ * Superlarge Density Ratios" (arXiv:1906.09530).
+ *
+ * One time step (Sec. 2-4 of the paper) on an nx x ny D2Q9 mesh, FP64:
+ *   1. moments rho = sum f_i, rho u = sum e_i f_i                     (Eq. 3)
+ *   2. bulk chemical potential psi'(rho) of the chosen EOS   (Eqs. 15/17/19/21)
+ *      bounded by an upper limit                                   (Sec. 5.6)
+ *   3. mesh chemical potential mu = k^2 psi'(rho) - kappa lap(rho)    (Eq. 33)
+ *      with derivatives from the periodic compact scheme     (Eqs. 37-39) and
+ *      the Laplacian as the first-derivative scheme applied twice   (Sec. 4.3)
+ *   4. nonideal force F = -rho grad mu + c_s^2 grad rho                (Eq. 12)
+ *   5. BGK collision with the exact-difference force term          (Eqs. 1, 5)
+ *      and streaming.
+ *
+ * Units: mesh lattice units (mesh step 1, time step 1, c_s^2 = 1/3).  The
+ * EOS constants, T and psi' live in momentum space; k links the two
+ * (Eq. 25) and enters only as the factor k^2 of Eq. 33.
+ *
+ * Layout: a scalar field is nx*ny doubles, row-major, node (x, y) at index
+ * y*nx + x.  The distribution state is 9 such planes, f[i][y][x], with the
+ * D2Q9 velocities e_0..e_8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
+ * (-1,-1),(1,-1) (Sec. 2).  The stored state is the pre-collision f(t).
+ *
+ * Boundaries: x is periodic.  y is periodic (bc_y = 0) or closed by
+ * half-way bounce-back walls at y = -1/2 and y = ny - 1/2 (bc_y = 1) that may
+ * slide along x with speed wall_ux; along y between walls the derivatives
+ * act on the even extension of each column about the walls, which gives the
+ * neighbour-node chemical-potential condition of Sec. 5.5.
+ *
+ * Streams: every device operation of a context is enqueued on the HIP
+ * stream given to lbm_init (NULL: the default stream).  Calls that return
+ * data to the host synchronise that stream.
+ *
+ * Errors: every entry point returns an lbm_status; nothing is thrown across
+ * the ABI.  LBM_E_NONFINITE is sticky: once a non-finite density has been
+ * seen, every later call on the context returns it.  lbm_last_error() gives
+ * a human-readable reason for the last failure of a context.
+ *
+ * Threading: a context may be used by one host thread at a time.
+ */
+#ifndef CPLBM_LBM_H
+#define CPLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_NOT_CONVERGED = 1,  /* run_until_converged reached max_steps */
+    LBM_E_INVALID = -1,     /* a parameter or size is outside what is supported */
+    LBM_E_DOMAIN = -2,      /* initial density outside the EOS domain */
+    LBM_E_NOMEM = -3,       /* device allocation failed or workspace too small */
+    LBM_E_DEVICE = -4,      /* a HIP call failed */
+    LBM_E_NONFINITE = -5    /* the density field became NaN or infinite */
+} lbm_status;
+
+/* Equations of state of Sec. 3.2. */
+typedef enum {
+    LBM_EOS_VDW = 0,  /* van der Waals, Eqs. 14-15 */
+    LBM_EOS_RK = 1,   /* Redlich-Kwong, alpha(T) = T^-1/2, Eqs. 16-17 */
+    LBM_EOS_RKS = 2,  /* Soave-Redlich-Kwong, Eqs. 16-17 */
+    LBM_EOS_PR = 3,   /* Peng-Robinson, Eqs. 18-19 */
+    LBM_EOS_CS = 4    /* Carnahan-Starling, Eqs. 20-21 */
+} lbm_eos;
+
+typedef struct {
+    int32_t nx, ny;     /* mesh nodes; 8 <= nx, ny <= 4096 */
+    int32_t bc_y;       /* 0: periodic in y; 1: bounce-back walls in y */
+    int32_t eos;        /* lbm_eos */
+    double a, b, R;     /* EOS constants in momentum space (Sec. 3.2) */
+    double omega;       /* acentric factor (RKS, PR) */
+    double T_r;         /* reduced temperature T/T_c, 0 < T_r < 1 */
+    double kappa;       /* surface-tension coefficient on the mesh, >= 0 (Eq. 33) */
+    double tau;         /* BGK relaxation time, > 1/2 (Eq. 1) */
+    double k;           /* proportional coefficient mesh/momentum step, > 0 (Eq. 25) */
+    double mu_cap;      /* upper limit of psi'(rho), momentum units (Sec. 5.6);
+                           +INFINITY switches it off */
+    double cfd_alpha;   /* compact scheme: 1/3 (sixth order, Eq. 39) or 1/4 (Eq. 38) */
+    double wall_ux;     /* x-velocity of both walls (bc_y = 1); 0 for resting walls */
+} lbm_params;
+
+/* ---- host-only thermodynamics (no device needed) ----------------------- */
+
+/* Critical point of the EOS in p (T_r is ignored): dp0/drho = d2p0/drho2 = 0
+ * with alpha(T_c) = 1 for RKS and PR and alpha = T^-1/2 for RK (Sec. 3.2).
+ * Outputs in momentum units; any output pointer may be NULL. */
+lbm_status lbm_critical_point(const lbm_params *p, double *T_c, double *rho_c, double *p_c);
+
+/* Maxwell equal-area coexistence densities at p->T_r: equal psi'(rho) and
+ * equal p0(rho) on both branches (Sec. 5.1).  Used to build the initial
+ * tanh fields of Eq. 41.  LBM_E_INVALID if T_r is not in (0, 1). */
+lbm_status lbm_maxwell(const lbm_params *p, double *rho_g, double *rho_l);
+
+/* ---- solver ----------------------------------------------------------- */
+
+/* Device bytes a context for these parameters needs (for device_ws). */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Create a context and set f = f^eq(rho0, u0) (Eq. 2).
+ *   rho0, ux0, uy0: nx*ny doubles each, host memory, or device memory when
+ *                   src_on_device != 0 (ux0/uy0 may be NULL for rest);
+ *                   read during the call only; caller keeps ownership.
+ *   hip_stream:     hipStream_t to enqueue on, or NULL for the default stream.
+ *   device_ws:      NULL (the library allocates) or a caller-owned device
+ *                   buffer of lbm_workspace_bytes(p) bytes, 256-byte aligned,
+ *                   that must outlive the context.
+ * Fails with LBM_E_INVALID for unsupported parameters, LBM_E_DOMAIN when a
+ * density is not positive and finite, or (with the limit switched off)
+ * outside the EOS domain (rho >= 1/b, or b rho / 4 >= 1 for CS).  *out is
+ * NULL on failure. */
+lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+                    int src_on_device, void *hip_stream, void *device_ws, lbm_ctx **out);
+
+/* Enqueue nsteps time steps (nsteps >= 0).  Returns once the work is
+ * enqueued; a non-finite state is only detected by the calls below. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Observables of the current state: rho, and the velocity
+ * v = u + F/(2 rho) (Sec. 2, after Eq. 5).  Each output holds nx*ny
+ * doubles in host memory, or device memory if dst_on_device != 0; any
+ * output may be NULL.  Synchronises the stream. */
+lbm_status lbm_moments(lbm_ctx *ctx, double *rho, double *vx, double *vy, int dst_on_device);
+
+/* The mesh chemical potential mu of Eq. 33 and the force F of Eq. 12 at
+ * the current state (same conventions as lbm_moments). */
+lbm_status lbm_force_fields(lbm_ctx *ctx, double *mu, double *Fx, double *Fy, int dst_on_device);
+
+/* Step until max_x |rho(t) - rho(t - check_every)| < tol, testing every
+ * check_every steps, at most max_steps steps.  Returns LBM_OK when
+ * converged, LBM_NOT_CONVERGED at max_steps, LBM_E_NONFINITE on a NaN or
+ * infinite density.  *steps_done and *last_delta may be NULL. */
+lbm_status lbm_run_until_converged(lbm_ctx *ctx, double tol, int64_t check_every,
+                                   int64_t max_steps, int64_t *steps_done, double *last_delta);
+
+/* Copy the state f[9][ny][nx] out of / into the context (checkpoint and
+ * resume; resuming reproduces a run bit for bit). */
+lbm_status lbm_get_state(lbm_ctx *ctx, double *f, int dst_on_device);
+lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
+
+/* Diagnostic: enqueue nsteps steps exactly like lbm_step, with a HIP event
+ * recorded on the context's stream before and after every kernel, and
+ * return the average device time of each pass in milliseconds:
+ * ms_per_pass[0] = row pass (rho, d2/dx2 rho), [1] = column pass (mu, F_y),
+ * [2] = row pass (F_x, collision, streaming).  Synchronises the stream. */
+lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
+
+/* Steps taken since lbm_init. */
+int64_t lbm_steps_taken(const lbm_ctx *ctx);
+
+/* Wait for all work of the context. */
+lbm_status lbm_synchronize(lbm_ctx *ctx);
+
+/* Release the context and the memory the library allocated for it. */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Reason for the last failure of ctx (or of the last failed lbm_init when
+ * ctx is NULL); empty when there was none.  Valid until the next call. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Name of a status code. */
+const char *lbm_status_string(lbm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPLBM_LBM_H */

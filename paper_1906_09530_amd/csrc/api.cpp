@@ -1,0 +1,558 @@
+// C ABI of the solver (include/lbm.h): context, memory, validation, the
+// time-step sequence and the convergence loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+#include "thermo.hpp"
+
+using namespace cplbm;
+
+struct lbm_ctx {
+    lbm_params prm{};
+    KParams kp{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool owns_mem = false;
+    void *mem = nullptr;
+    size_t N = 0;
+    double *f[2] = {nullptr, nullptr};
+    int cur = 0;  // f[cur] holds the current state
+    double *rho = nullptr, *dxx = nullptr, *mu = nullptr, *fy = nullptr;
+    double *prev = nullptr, *obs = nullptr, *partial = nullptr, *red = nullptr;
+    int red_blocks = 1;
+    int64_t steps = 0;
+    lbm_status sticky = LBM_OK;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kMaxLine = kBlockElems;  // longest line a block holds in LDS
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t f, field, partial, red, total;
+};
+
+Layout layout_for(const lbm_params *p, int red_blocks)
+{
+    Layout L;
+    const size_t N = (size_t)p->nx * p->ny;
+    L.f = align256(9 * N * sizeof(double));
+    L.field = align256(N * sizeof(double));
+    L.partial = align256(2 * (size_t)red_blocks * sizeof(double));
+    L.red = align256(2 * sizeof(double));
+    // f A/B, rho, dxx, mu, fy, prev, 3 observation planes, partials, result
+    L.total = 2 * L.f + 8 * L.field + L.partial + L.red;
+    return L;
+}
+
+lbm_status fail(lbm_ctx *c, lbm_status s, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_init_error = msg;
+    return s;
+}
+
+#define HIP_OR(c, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((c), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite(double v) { return std::isfinite(v); }
+
+lbm_status validate(const lbm_params *p, std::string *why)
+{
+    auto bad = [&](const char *m) {
+        *why = m;
+        return LBM_E_INVALID;
+    };
+    if (!p) return bad("params is NULL");
+    if (p->nx < 8 || p->ny < 8 || p->nx > kMaxLine || p->ny > kMaxLine)
+        return bad("nx and ny must lie in [8, 4096]");
+    if (p->bc_y != 0 && p->bc_y != 1) return bad("bc_y must be 0 or 1");
+    if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS) return bad("unknown EOS");
+    if (!(finite(p->a) && p->a > 0 && finite(p->b) && p->b > 0 && finite(p->R) && p->R > 0))
+        return bad("a, b, R must be positive and finite");
+    if (!finite(p->omega)) return bad("omega must be finite");
+    if (!(finite(p->T_r) && p->T_r > 0)) return bad("T_r must be positive");
+    if (!(finite(p->kappa) && p->kappa >= 0)) return bad("kappa must be >= 0");
+    if (!(finite(p->tau) && p->tau > 0.5)) return bad("tau must exceed 1/2");
+    if (!(finite(p->k) && p->k > 0)) return bad("k must be positive");
+    if (std::isnan(p->mu_cap)) return bad("mu_cap is NaN");
+    if (!finite(p->wall_ux)) return bad("wall_ux must be finite");
+    if (std::fabs(p->cfd_alpha - 1.0 / 3.0) > 1e-15 && std::fabs(p->cfd_alpha - 0.25) > 1e-15)
+        return bad("cfd_alpha must be 1/3 or 1/4");
+    return LBM_OK;
+}
+
+Eos eos_of(const lbm_params *p)
+{
+    return Eos{p->eos, (long double)p->a, (long double)p->b, (long double)p->R,
+               (long double)p->omega};
+}
+
+// Device parameter block: temperature, alpha(T), compact-scheme and
+// reduction-stage coefficients, block shapes.
+bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
+{
+    Eos e = eos_of(p);
+    long double Tc, rc, pc;
+    if (!eos_critical(e, &Tc, &rc, &pc)) {
+        *why = "critical point not found";
+        return false;
+    }
+    const long double T = (long double)p->T_r * Tc;
+    KParams k{};
+    k.nx = p->nx;
+    k.ny = p->ny;
+    k.bc_y = p->bc_y;
+    k.eos = p->eos;
+    k.rows_per_block = kMaxLine / p->nx;
+    k.cols_per_block = kMaxLine / p->ny;
+    k.kappa_zero = p->kappa == 0.0;
+    k.a = p->a;
+    k.b = p->b;
+    k.RT = (double)((long double)p->R * T);
+    k.A = (double)((long double)p->a * eos_alpha(e, T, Tc));
+    k.k2 = p->k * p->k;
+    k.kappa = p->kappa;
+    k.inv_tau = 1.0 / p->tau;
+    k.mu_cap = p->mu_cap;
+    k.wall_ux = p->wall_ux;
+    const long double al = std::fabs(p->cfd_alpha - 0.25) < 1e-15 ? 0.25L : 1.0L / 3.0L;
+    k.cfd_a2 = (double)(2.0L * (al + 2.0L) / 3.0L / 2.0L);  // a/2, Eq. 38
+    k.cfd_b4 = (double)((4.0L * al - 1.0L) / 3.0L / 4.0L);  // b/4, Eq. 38
+    long double c = al;
+    int s = 0;
+    while (s < kMaxStages) {
+        long double g = 1.0L / (1.0L - 2.0L * c * c);
+        k.pcr_c[s] = (double)c;
+        k.pcr_g[s] = (double)g;
+        ++s;
+        c = -c * c * g;
+        if (std::fabs((double)c) < 1e-18) break;
+    }
+    k.nstage = s;
+    *kp = k;
+    return true;
+}
+
+lbm_status check_density(const lbm_params *p, const double *rho, const double *ux,
+                         const double *uy, size_t N, std::string *why)
+{
+    const bool cap_off = std::isinf(p->mu_cap) && p->mu_cap > 0;
+    for (size_t n = 0; n < N; ++n) {
+        const double r = rho[n];
+        if (!(finite(r) && r > 0)) {
+            *why = "initial density must be positive and finite";
+            return LBM_E_DOMAIN;
+        }
+        if (cap_off) {
+            const bool outside = p->eos == LBM_EOS_CS ? p->b * r * 0.25 >= 1.0 : p->b * r >= 1.0;
+            if (outside) {
+                *why = "initial density outside the EOS domain and no upper limit of mu";
+                return LBM_E_DOMAIN;
+            }
+        }
+        if ((ux && !finite(ux[n])) || (uy && !finite(uy[n]))) {
+            *why = "initial velocity must be finite";
+            return LBM_E_DOMAIN;
+        }
+    }
+    return LBM_OK;
+}
+
+void carve(lbm_ctx *c, int red_blocks)
+{
+    Layout L = layout_for(&c->prm, red_blocks);
+    char *m = (char *)c->mem;
+    c->f[0] = (double *)m;
+    m += L.f;
+    c->f[1] = (double *)m;
+    m += L.f;
+    double **fields[] = {&c->rho, &c->dxx, &c->mu, &c->fy, &c->prev};
+    for (double **q : fields) {
+        *q = (double *)m;
+        m += L.field;
+    }
+    c->obs = (double *)m;
+    m += 3 * L.field;
+    c->partial = (double *)m;
+    m += L.partial;
+    c->red = (double *)m;
+}
+
+lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
+{
+    for (int64_t s = 0; s < n; ++s) {
+        const double *fc = c->f[c->cur];
+        double *fn = c->f[1 - c->cur];
+        HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream));
+        HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream));
+        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream));
+        c->cur = 1 - c->cur;
+        c->steps += 1;
+    }
+    return LBM_OK;
+}
+
+// rho, mu and F_y of the current state into the context's field buffers.
+lbm_status enqueue_fields(lbm_ctx *c)
+{
+    const double *fc = c->f[c->cur];
+    HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream));
+    HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream));
+    return LBM_OK;
+}
+
+lbm_status copy_out(lbm_ctx *c, double *dst, const double *src, size_t n, int on_device)
+{
+    if (!dst) return LBM_OK;
+    HIP_OR(c, hipMemcpyAsync(dst, src, n * sizeof(double),
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    return LBM_OK;
+}
+
+lbm_status enter(lbm_ctx *c)
+{
+    if (!c) return LBM_E_INVALID;
+    if (c->sticky != LBM_OK) return c->sticky;
+    HIP_OR(c, hipSetDevice(c->device));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_critical_point(const lbm_params *p, double *T_c, double *rho_c, double *p_c)
+{
+    if (!p || p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS || !(p->a > 0 && p->b > 0 && p->R > 0))
+        return fail(nullptr, LBM_E_INVALID, "invalid EOS parameters");
+    long double Tc, rc, pc;
+    if (!eos_critical(eos_of(p), &Tc, &rc, &pc))
+        return fail(nullptr, LBM_E_INVALID, "critical point not found");
+    if (T_c) *T_c = (double)Tc;
+    if (rho_c) *rho_c = (double)rc;
+    if (p_c) *p_c = (double)pc;
+    return LBM_OK;
+}
+
+lbm_status lbm_maxwell(const lbm_params *p, double *rho_g, double *rho_l)
+{
+    if (!p || p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS || !(p->a > 0 && p->b > 0 && p->R > 0))
+        return fail(nullptr, LBM_E_INVALID, "invalid EOS parameters");
+    if (!(p->T_r > 0 && p->T_r < 1)) return fail(nullptr, LBM_E_INVALID, "T_r must lie in (0, 1)");
+    long double g, l;
+    if (!eos_maxwell(eos_of(p), (long double)p->T_r, &g, &l))
+        return fail(nullptr, LBM_E_INVALID, "Maxwell construction failed");
+    if (rho_g) *rho_g = (double)g;
+    if (rho_l) *rho_l = (double)l;
+    return LBM_OK;
+}
+
+size_t lbm_workspace_bytes(const lbm_params *p)
+{
+    std::string why;
+    if (validate(p, &why) != LBM_OK) return 0;
+    KParams kp;
+    if (!make_kparams(p, &kp, &why)) return 0;
+    return layout_for(p, rho_delta_blocks(kp)).total;
+}
+
+lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+                    int src_on_device, void *hip_stream, void *device_ws, lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    g_init_error.clear();
+    std::string why;
+    lbm_status st = validate(p, &why);
+    if (st != LBM_OK) return fail(nullptr, st, why);
+    if (!rho0) return fail(nullptr, LBM_E_INVALID, "rho0 is NULL");
+    KParams kp;
+    if (!make_kparams(p, &kp, &why)) return fail(nullptr, LBM_E_INVALID, why);
+    const size_t N = (size_t)p->nx * p->ny;
+
+    // validate the initial fields on the host
+    std::vector<double> h_rho, h_ux, h_uy;
+    const double *vr = rho0, *vx = ux0, *vy = uy0;
+    if (src_on_device) {
+        h_rho.resize(N);
+        if (hipMemcpy(h_rho.data(), rho0, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(nullptr, LBM_E_DEVICE, "reading rho0 from the device failed");
+        vr = h_rho.data();
+        if (ux0) {
+            h_ux.resize(N);
+            if (hipMemcpy(h_ux.data(), ux0, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(nullptr, LBM_E_DEVICE, "reading ux0 from the device failed");
+            vx = h_ux.data();
+        }
+        if (uy0) {
+            h_uy.resize(N);
+            if (hipMemcpy(h_uy.data(), uy0, N * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+                return fail(nullptr, LBM_E_DEVICE, "reading uy0 from the device failed");
+            vy = h_uy.data();
+        }
+    }
+    st = check_density(p, vr, vx, vy, N, &why);
+    if (st != LBM_OK) return fail(nullptr, st, why);
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->prm = *p;
+    c->kp = kp;
+    c->N = N;
+    c->stream = (hipStream_t)hip_stream;
+    c->red_blocks = rho_delta_blocks(kp);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_E_DEVICE, "no HIP device");
+    }
+    const size_t bytes = layout_for(p, c->red_blocks).total;
+    if (device_ws) {
+        if (((uintptr_t)device_ws & 255) != 0) {
+            delete c;
+            return fail(nullptr, LBM_E_INVALID, "device_ws must be 256-byte aligned");
+        }
+        c->mem = device_ws;
+    } else {
+        if (hipMalloc(&c->mem, bytes) != hipSuccess) {
+            delete c;
+            return fail(nullptr, LBM_E_NOMEM, "hipMalloc of the workspace failed");
+        }
+        c->owns_mem = true;
+    }
+    carve(c, c->red_blocks);
+
+    // initial fields to the device (the observation planes serve as staging)
+    const double *d_rho = rho0, *d_ux = ux0, *d_uy = uy0;
+    hipError_t e = hipSuccess;
+    if (!src_on_device) {
+        e = hipMemcpyAsync(c->obs, rho0, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        d_rho = c->obs;
+        if (e == hipSuccess && ux0) {
+            e = hipMemcpyAsync(c->obs + N, ux0, N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            d_ux = c->obs + N;
+        }
+        if (e == hipSuccess && uy0) {
+            e = hipMemcpyAsync(c->obs + 2 * N, uy0, N * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream);
+            d_uy = c->obs + 2 * N;
+        }
+    }
+    if (e == hipSuccess) e = launch_init_feq(kp, d_rho, d_ux, d_uy, c->f[0], c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("initialisation on the device failed: ") + hipGetErrorString(e);
+        lbm_destroy(c);
+        return fail(nullptr, LBM_E_DEVICE, m);
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (nsteps < 0) return fail(c, LBM_E_INVALID, "nsteps must be >= 0");
+    return enqueue_steps(c, nsteps);
+}
+
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *vx, double *vy, int dst_on_device)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if ((st = enqueue_fields(c)) != LBM_OK) return st;
+    const size_t N = c->N;
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, c->obs, c->obs + N,
+                                  c->obs + 2 * N, nullptr, c->stream));
+    if ((st = copy_out(c, rho, c->obs, N, dst_on_device)) != LBM_OK) return st;
+    if ((st = copy_out(c, vx, c->obs + N, N, dst_on_device)) != LBM_OK) return st;
+    if ((st = copy_out(c, vy, c->obs + 2 * N, N, dst_on_device)) != LBM_OK) return st;
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_force_fields(lbm_ctx *c, double *mu, double *Fx, double *Fy, int dst_on_device)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if ((st = enqueue_fields(c)) != LBM_OK) return st;
+    const size_t N = c->N;
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, nullptr, nullptr, nullptr,
+                                  c->obs, c->stream));
+    if ((st = copy_out(c, mu, c->mu, N, dst_on_device)) != LBM_OK) return st;
+    if ((st = copy_out(c, Fx, c->obs, N, dst_on_device)) != LBM_OK) return st;
+    if ((st = copy_out(c, Fy, c->fy, N, dst_on_device)) != LBM_OK) return st;
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_run_until_converged(lbm_ctx *c, double tol, int64_t check_every, int64_t max_steps,
+                                   int64_t *steps_done, double *last_delta)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (check_every <= 0 || max_steps < 0 || !(tol >= 0))
+        return fail(c, LBM_E_INVALID, "check_every > 0, max_steps >= 0, tol >= 0 required");
+    double res[2] = {0.0, 0.0};
+    HIP_OR(c, launch_rho_delta(c->kp, c->f[c->cur], c->prev, c->partial, c->red_blocks, c->red,
+                               c->stream));
+    int64_t done = 0;
+    double delta = INFINITY;
+    st = LBM_NOT_CONVERGED;
+    while (done < max_steps) {
+        int64_t n = check_every;
+        if (done + n > max_steps) n = max_steps - done;
+        lbm_status s2 = enqueue_steps(c, n);
+        if (s2 != LBM_OK) return s2;
+        done += n;
+        HIP_OR(c, launch_rho_delta(c->kp, c->f[c->cur], c->prev, c->partial, c->red_blocks,
+                                   c->red, c->stream));
+        HIP_OR(c, hipMemcpyAsync(res, c->red, sizeof(res), hipMemcpyDeviceToHost, c->stream));
+        HIP_OR(c, hipStreamSynchronize(c->stream));
+        delta = res[0];
+        if (res[1] != 0.0) {
+            c->sticky = LBM_E_NONFINITE;
+            c->err = "non-finite density after " + std::to_string(c->steps) + " steps";
+            delta = NAN;
+            st = LBM_E_NONFINITE;
+            break;
+        }
+        if (n == check_every && delta < tol) {
+            st = LBM_OK;
+            break;
+        }
+    }
+    if (steps_done) *steps_done = done;
+    if (last_delta) *last_delta = delta;
+    return st;
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, double *f, int dst_on_device)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (!f) return fail(c, LBM_E_INVALID, "f is NULL");
+    if ((st = copy_out(c, f, c->f[c->cur], 9 * c->N, dst_on_device)) != LBM_OK) return st;
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const double *f, int src_on_device)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (!f) return fail(c, LBM_E_INVALID, "f is NULL");
+    HIP_OR(c, hipMemcpyAsync(c->f[c->cur], f, 9 * c->N * sizeof(double),
+                             src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (nsteps <= 0 || !ms_per_pass) return fail(c, LBM_E_INVALID, "nsteps > 0 and an output required");
+    constexpr int kChunk = 256;
+    std::vector<hipEvent_t> ev(4 * kChunk, nullptr);
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &q : ev)
+                if (q) (void)hipEventDestroy(q);
+            return fail(c, LBM_E_DEVICE, "hipEventCreate failed");
+        }
+    double acc[3] = {0, 0, 0};
+    hipError_t err = hipSuccess;
+    for (int64_t done = 0; done < nsteps && err == hipSuccess;) {
+        const int n = (int)std::min<int64_t>(kChunk, nsteps - done);
+        for (int s = 0; s < n && err == hipSuccess; ++s) {
+            const double *fc = c->f[c->cur];
+            double *fn = c->f[1 - c->cur];
+            hipEvent_t *e = &ev[4 * s];
+            if (err == hipSuccess) err = hipEventRecord(e[0], c->stream);
+            if (err == hipSuccess) err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[1], c->stream);
+            if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[2], c->stream);
+            if (err == hipSuccess) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
+            c->cur = 1 - c->cur;
+            c->steps += 1;
+        }
+        if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+        for (int s = 0; s < n && err == hipSuccess; ++s)
+            for (int q = 0; q < 3 && err == hipSuccess; ++q) {
+                float ms = 0.f;
+                err = hipEventElapsedTime(&ms, ev[4 * s + q], ev[4 * s + q + 1]);
+                acc[q] += ms;
+            }
+        done += n;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess)
+        return fail(c, LBM_E_DEVICE, std::string("pass timing failed: ") + hipGetErrorString(err));
+    for (int q = 0; q < 3; ++q) ms_per_pass[q] = acc[q] / (double)nsteps;
+    return LBM_OK;
+}
+
+int64_t lbm_steps_taken(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+lbm_status lbm_synchronize(lbm_ctx *c)
+{
+    if (!c) return LBM_E_INVALID;
+    HIP_OR(c, hipSetDevice(c->device));
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return c->sticky;
+}
+
+void lbm_destroy(lbm_ctx *c)
+{
+    if (!c) return;
+    if (c->owns_mem && c->mem) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->mem);
+    }
+    delete c;
+}
+
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+const char *lbm_status_string(lbm_status s)
+{
+    switch (s) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_NOT_CONVERGED: return "LBM_NOT_CONVERGED";
+    case LBM_E_INVALID: return "LBM_E_INVALID";
+    case LBM_E_DOMAIN: return "LBM_E_DOMAIN";
+    case LBM_E_NOMEM: return "LBM_E_NOMEM";
+    case LBM_E_DEVICE: return "LBM_E_DEVICE";
+    case LBM_E_NONFINITE: return "LBM_E_NONFINITE";
+    }
+    return "unknown";
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+"""ctypes binding of libcplbm (the C ABI declared in include/lbm.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Host data are numpy float64 arrays; device data are torch
+tensors (float64, contiguous, on the GPU), whose pointers are passed as-is.
+If the library is not built, ``load()`` raises -- there is no fallback.
+"""
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcplbm.so")
+
+LBM_OK, LBM_NOT_CONVERGED = 0, 1
+LBM_E_INVALID, LBM_E_DOMAIN, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE = -1, -2, -3, -4, -5
+EOS_VDW, EOS_RK, EOS_RKS, EOS_PR, EOS_CS = 0, 1, 2, 3, 4
+
+# EOS constants of Sec. 3.2 (a, b), R = 1
+EOS_AB = {EOS_VDW: (9 / 49, 2 / 21), EOS_RK: (2 / 49, 2 / 21), EOS_RKS: (2 / 49, 2 / 21),
+          EOS_PR: (2 / 49, 2 / 21), EOS_CS: (1.0, 4.0)}
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("bc_y", C.c_int32), ("eos", C.c_int32),
+        ("a", C.c_double), ("b", C.c_double), ("R", C.c_double), ("omega", C.c_double),
+        ("T_r", C.c_double), ("kappa", C.c_double), ("tau", C.c_double), ("k", C.c_double),
+        ("mu_cap", C.c_double), ("cfd_alpha", C.c_double), ("wall_ux", C.c_double),
+    ]
+
+
+def params(eos, T_r, nx, ny, *, kappa, tau, k, mu_cap=math.inf, cfd_alpha=1.0 / 3.0, bc_y=0,
+           wall_ux=0.0, omega=0.344, a=None, b=None, R=1.0):
+    da, db = EOS_AB[eos]
+    return Params(nx=nx, ny=ny, bc_y=bc_y, eos=eos, a=da if a is None else a,
+                  b=db if b is None else b, R=R, omega=omega, T_r=T_r, kappa=kappa, tau=tau,
+                  k=k, mu_cap=mu_cap, cfd_alpha=cfd_alpha, wall_ux=wall_ux)
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (status_string(status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libcplbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcplbm.so is not built (run python -m paper_1906_09530_amd.build)")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one copy, so device buffers and
+    # streams are shared with torch (a second runtime copy would be loaded if
+    # the order were reversed, and torch could then not see the GPU).
+    import torch  # noqa: F401
+    lib = C.CDLL(LIB_PATH)
+    P, d, i32, i64 = C.c_void_p, C.c_double, C.c_int, C.c_int64
+    pp = C.POINTER(Params)
+    pd = C.POINTER(C.c_double)
+    sigs = {
+        "lbm_critical_point": (i32, [pp, pd, pd, pd]),
+        "lbm_maxwell": (i32, [pp, pd, pd]),
+        "lbm_workspace_bytes": (C.c_size_t, [pp]),
+        "lbm_init": (i32, [pp, P, P, P, i32, P, P, C.POINTER(P)]),
+        "lbm_step": (i32, [P, i64]),
+        "lbm_moments": (i32, [P, P, P, P, i32]),
+        "lbm_force_fields": (i32, [P, P, P, P, i32]),
+        "lbm_run_until_converged": (i32, [P, d, i64, i64, C.POINTER(i64), pd]),
+        "lbm_get_state": (i32, [P, P, i32]),
+        "lbm_set_state": (i32, [P, P, i32]),
+        "lbm_time_passes": (i32, [P, i64, pd]),
+        "lbm_steps_taken": (i64, [P]),
+        "lbm_synchronize": (i32, [P]),
+        "lbm_destroy": (None, [P]),
+        "lbm_last_error": (C.c_char_p, [P]),
+        "lbm_status_string": (C.c_char_p, [i32]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(s):
+    return load().lbm_status_string(s).decode()
+
+
+def _check(st, ctx=None, ok=(LBM_OK,)):
+    if st not in ok:
+        raise LBMError(st, load().lbm_last_error(ctx).decode())
+    return st
+
+
+def critical_point(p):
+    Tc, rc, pc = C.c_double(), C.c_double(), C.c_double()
+    _check(load().lbm_critical_point(C.byref(p), C.byref(Tc), C.byref(rc), C.byref(pc)))
+    return Tc.value, rc.value, pc.value
+
+
+def maxwell(p):
+    g, l = C.c_double(), C.c_double()
+    _check(load().lbm_maxwell(C.byref(p), C.byref(g), C.byref(l)))
+    return g.value, l.value
+
+
+def workspace_bytes(p):
+    return load().lbm_workspace_bytes(C.byref(p))
+
+
+def _is_device(a):
+    return a is not None and hasattr(a, "data_ptr") and getattr(a, "is_cuda", False)
+
+
+def _ptr(a):
+    """Pointer of a host numpy array or a device torch tensor (float64, contiguous)."""
+    if a is None:
+        return None
+    if _is_device(a):
+        import torch
+        assert a.dtype == torch.float64 and a.is_contiguous()
+        return a.data_ptr()
+    assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data
+
+
+class Solver:
+    """One simulation (an lbm_ctx)."""
+
+    def __init__(self, p, rho0, ux0=None, uy0=None, stream=None, device_ws=None):
+        lib = load()
+        self.p = p
+        self.shape = (p.ny, p.nx)
+        on_dev = _is_device(rho0)
+        if not on_dev:
+            rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+            ux0 = None if ux0 is None else np.ascontiguousarray(ux0, dtype=np.float64)
+            uy0 = None if uy0 is None else np.ascontiguousarray(uy0, dtype=np.float64)
+        self._keep = (rho0, ux0, uy0, device_ws)
+        ctx = C.c_void_p()
+        st = lib.lbm_init(C.byref(p), _ptr(rho0), _ptr(ux0), _ptr(uy0), int(on_dev), stream,
+                          None if device_ws is None else device_ws.data_ptr(), C.byref(ctx))
+        _check(st, None)
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(load().lbm_step(self.ctx, int(n)), self.ctx)
+
+    def synchronize(self):
+        _check(load().lbm_synchronize(self.ctx), self.ctx)
+
+    @property
+    def steps_taken(self):
+        return load().lbm_steps_taken(self.ctx)
+
+    def _outs(self, k, device):
+        if device:
+            import torch
+            return [torch.empty(self.shape, dtype=torch.float64, device="cuda") for _ in range(k)]
+        return [np.empty(self.shape) for _ in range(k)]
+
+    def moments(self, device=False):
+        """(rho, vx, vy) with v = u + F/(2 rho)."""
+        r, vx, vy = self._outs(3, device)
+        _check(load().lbm_moments(self.ctx, _ptr(r), _ptr(vx), _ptr(vy), int(device)), self.ctx)
+        return r, vx, vy
+
+    def force_fields(self, device=False):
+        """(mu, Fx, Fy): mesh chemical potential (Eq. 33) and force (Eq. 12)."""
+        mu, fx, fy = self._outs(3, device)
+        _check(load().lbm_force_fields(self.ctx, _ptr(mu), _ptr(fx), _ptr(fy), int(device)),
+               self.ctx)
+        return mu, fx, fy
+
+    def run_until_converged(self, tol, check_every=100, max_steps=10 ** 7):
+        steps, delta = C.c_int64(), C.c_double()
+        st = load().lbm_run_until_converged(self.ctx, tol, int(check_every), int(max_steps),
+                                            C.byref(steps), C.byref(delta))
+        _check(st, self.ctx, ok=(LBM_OK, LBM_NOT_CONVERGED))
+        return st, steps.value, delta.value
+
+    def time_passes(self, n):
+        """Average device ms of the three passes of a step over n steps."""
+        out = (C.c_double * 3)()
+        _check(load().lbm_time_passes(self.ctx, int(n), out), self.ctx)
+        return list(out)
+
+    def get_state(self, device=False):
+        if device:
+            import torch
+            f = torch.empty((9,) + self.shape, dtype=torch.float64, device="cuda")
+        else:
+            f = np.empty((9,) + self.shape)
+        _check(load().lbm_get_state(self.ctx, _ptr(f), int(device)), self.ctx)
+        return f
+
+    def set_state(self, f):
+        dev = _is_device(f)
+        if not dev:
+            f = np.ascontiguousarray(f, dtype=np.float64)
+        _check(load().lbm_set_state(self.ctx, _ptr(f), int(dev)), self.ctx)
