@@ -71,7 +71,20 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=1000,
                     help="steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
+                         "traffic, to calibrate FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        n = args.copy_calib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calib_bytes_per_dispatch": n * 8}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is a single-GPU build "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -93,6 +106,8 @@ def main():
     print("warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
     s.step(args.warmup)
     torch.cuda.synchronize()
+    tune = s.autotune(20)
+    print("column-strip widths (ms): %s" % tune, file=sys.stderr, flush=True)
 
     print("timed %d steps" % args.steps, file=sys.stderr, flush=True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -160,6 +175,7 @@ def main():
         "kernels": {PASS_NAMES[i]: {"avg_ms": round(pass_ms[i], 6), "GB_s": round(gbs[i], 1),
                                     "bytes_per_node": PASS_BYTES[i]} for i in range(3)},
         "step_algorithmic_GB_s": round(sum(PASS_BYTES) * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
+        "autotune_col_width_ms": {str(k): round(v, 6) for k, v in tune.items()},
         "wall_s": round(wall, 3),
         "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
                   "rho_corner": float(outside), "max_speed": float(np.hypot(vx, vy).max()),

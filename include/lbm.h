@@ -153,6 +153,24 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
  * [2] = row pass (F_x, collision, streaming).  Synchronises the stream. */
 lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
 
+/* Autotuner: time the column pass of the current state for each strip width
+ * (columns per workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS
+ * holds and, for the factorised solve, each chunk length (column nodes per
+ * thread) in {4, 8, 16}; `repeats` launches each (HIP events); keep the
+ * fastest for the context.  The state f is not changed.  widths[],
+ * chunks[] and ms[] (room for 15 entries each, may be NULL) receive the
+ * candidates (chunk 0: general reduction kernel) and their average time in
+ * milliseconds; *count (may be NULL) their number.  Synchronises. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, double *ms,
+                        int *count);
+
+/* Set the column-pass shape directly (width in columns per workgroup, chunk
+ * in column nodes per thread of the factorised solve, 0 for the general
+ * reduction kernel).  LBM_E_INVALID if the shape does not fit one workgroup
+ * or the chunk is not 0, 4, 8 or 16.  Results of every shape agree to
+ * round-off. */
+lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
+
 /* Steps taken since lbm_init. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 

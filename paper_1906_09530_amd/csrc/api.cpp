@@ -38,7 +38,9 @@ namespace {
 
 thread_local std::string g_init_error;
 
-constexpr int kMaxLine = kBlockElems;  // longest line a block holds in LDS
+constexpr int kMaxLine = kMaxBlockElems;  // longest line a block holds in LDS
+constexpr int kDefaultStripWidth = 4;     // columns per block before tuning
+constexpr int kDefaultChunk = 4;          // column nodes per thread before tuning
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -124,8 +126,6 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     k.ny = p->ny;
     k.bc_y = p->bc_y;
     k.eos = p->eos;
-    k.rows_per_block = kMaxLine / p->nx;
-    k.cols_per_block = kMaxLine / p->ny;
     k.kappa_zero = p->kappa == 0.0;
     k.a = p->a;
     k.b = p->b;
@@ -150,6 +150,22 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
         if (std::fabs((double)c) < 1e-18) break;
     }
     k.nstage = s;
+    if (s > 6) {  // the compare-only index folding assumes offsets <= 32
+        *why = "too many reduction stages";
+        return false;
+    }
+    // factorised inverse: q is the root of al q^2 + q + al = 0 with |q| < 1
+    const long double q = (-1.0L + sqrtl(1.0L - 4.0L * al * al)) / (2.0L * al);
+    k.iir_q = (double)q;
+    k.iir_inv_q = (double)(1.0L / q);
+    k.iir_K = (double)(1.0L / (1.0L + 2.0L * al * q));
+    long double qp = 1.0L;
+    for (int i = 0; i < 17; ++i) {
+        k.iir_qp[i] = (double)qp;
+        qp *= q;
+    }
+    set_row_shape(&k);
+    set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
     *kp = k;
     return true;
 }
@@ -515,6 +531,76 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
     if (err != hipSuccess)
         return fail(c, LBM_E_DEVICE, std::string("pass timing failed: ") + hipGetErrorString(err));
     for (int q = 0; q < 3; ++q) ms_per_pass[q] = acc[q] / (double)nsteps;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, double *ms,
+                        int *count)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (repeats <= 0) return fail(c, LBM_E_INVALID, "repeats must be positive");
+    // the column pass reads rho and d2/dx2 rho and writes mu and F_y only,
+    // so timing it repeatedly leaves the state untouched
+    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->rho, c->dxx, c->stream));
+    hipEvent_t e0, e1;
+    HIP_OR(c, hipEventCreate(&e0));
+    HIP_OR(c, hipEventCreate(&e1));
+    const int cand_w[] = {1, 2, 4, 8, 16};
+    const int cand_c[] = {4, 8, 16};
+    int n = 0, best_w = c->kp.cols_per_block, best_c = c->kp.col_lc;
+    double best = INFINITY;
+    hipError_t err = hipSuccess;
+    for (int cw = 0; cw < 15 && err == hipSuccess; ++cw) {
+        const int w = cand_w[cw / 3], ch = cand_c[cw % 3];
+        KParams kp = c->kp;
+        set_col_shape(&kp, w, ch);
+        if (kp.cols_per_block != w) continue;  // does not fit one block
+        // the general kernel ignores the chunk length: time it once
+        if (!kp.use_iir_cols && ch != cand_c[0]) continue;
+        err = launch_cols_mu(kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < repeats && err == hipSuccess; ++r)
+            err = launch_cols_mu(kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) break;
+        const double avg = t / repeats;
+        if (widths) widths[n] = w;
+        if (chunks) chunks[n] = kp.use_iir_cols ? ch : 0;
+        if (ms) ms[n] = avg;
+        ++n;
+        if (avg < best) {
+            best = avg;
+            best_w = w;
+            best_c = ch;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return fail(c, LBM_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(err));
+    set_col_shape(&c->kp, best_w, best_c);
+    if (count) *count = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (chunk != 0 && chunk != 4 && chunk != 8 && chunk != 16)
+        return fail(c, LBM_E_INVALID, "chunk must be 0, 4, 8 or 16");
+    KParams kp = c->kp;
+    set_col_shape(&kp, width, chunk == 0 ? 4 : chunk);
+    if (kp.cols_per_block != width) return fail(c, LBM_E_INVALID, "width does not fit a workgroup");
+    if (chunk == 0)
+        kp.use_iir_cols = 0;
+    else if (!kp.use_iir_cols)
+        return fail(c, LBM_E_INVALID, "this column length cannot use the factorised solve");
+    c->kp = kp;
     return LBM_OK;
 }
 

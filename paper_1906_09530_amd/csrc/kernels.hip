@@ -29,88 +29,44 @@
 // extended position returns the mirrored value times the parity of the
 // quantity (+1 for rho, mu, second derivatives; -1 for first derivatives
 // and their right-hand sides).
+#include <cmath>
+
 #include "kernels.hpp"
+#include "physics.hpp"
 
 namespace cplbm {
 
 namespace {
 
-// D2Q9 (Sec. 2)
-__device__ constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__device__ constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-__device__ constexpr double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
-                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-constexpr double CS2 = 1.0 / 3.0;
+using namespace phys;
 
-// rho = sum f_i in a fixed order (every pass computes it the same way).
-__device__ __forceinline__ double sum9(const double (&fi)[9])
-{
-    double r = fi[0];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) r += fi[i];
-    return r;
-}
-
-__device__ __forceinline__ void load9(const double *__restrict__ f, size_t N, size_t node,
-                                      double (&fi)[9])
-{
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fi[i] = f[i * N + node];
-}
-
-// Equilibrium of Eq. 2 with c_s^2 = 1/3.
-__device__ __forceinline__ double feq(int i, double rho, double ux, double uy, double uu)
-{
-    const double eu = EX[i] * ux + EY[i] * uy;
-    return WT[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-}
-
-// psi'(rho) of Eqs. 15, 17, 19, 21, bounded by the upper limit (Sec. 5.6):
-// outside the EOS domain, or when the formula gives NaN, the limit is used.
-__device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
-{
-    const double b = p.b, RT = p.RT, A = p.A;
-    const bool outside = (p.eos == 4) ? (b * rho * 0.25 >= 1.0) : (b * rho >= 1.0);
-    if (outside) return p.mu_cap;
-    double m;
-    switch (p.eos) {
-    case 0:  // van der Waals
-        m = RT * (log(rho / (1.0 - b * rho)) + 1.0 / (1.0 - b * rho)) - 2.0 * p.a * rho;
-        break;
-    case 1:
-    case 2:  // Redlich-Kwong, Soave-Redlich-Kwong
-        m = RT * log(rho / (1.0 - b * rho)) + RT / (1.0 - b * rho) - A / b * log(1.0 + b * rho) -
-            A * rho / (1.0 + b * rho);
-        break;
-    case 3: {  // Peng-Robinson
-        const double s2 = 1.4142135623730950488;
-        m = RT * log(rho / (1.0 - b * rho)) -
-            A / (2.0 * s2 * b) * log((s2 - 1.0 + b * rho) / (s2 + 1.0 - b * rho)) +
-            RT / (1.0 - b * rho) - A * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
-        break;
-    }
-    default: {  // Carnahan-Starling
-        const double eta = b * rho * 0.25, q = 1.0 - eta;
-        m = RT * ((3.0 - eta) / (q * q * q) + log(rho) + 1.0) - 2.0 * p.a * rho;
-        break;
-    }
-    }
-    if (isnan(m)) return p.mu_cap;
-    return m < p.mu_cap ? m : p.mu_cap;
-}
 
 // Lines held by a block in LDS.  Element e of the block is LDS slot e:
 // row layout slot = l * n + j, column layout slot = j * nl + l.
+// FAST: lines of at least kFastMinLine = 64 nodes.  Every offset the solve
+// uses is at most 2^(nstage-1) <= 32 (nstage <= 6, checked on the host) or 2
+// (right-hand side), so an index leaves [0, n) by less than n and folds back
+// by one compare instead of a modulo.
+template <bool FAST>
 struct LineMap {
-    int n;       // stored length of each line
-    int period;  // n (periodic) or 2 n (even extension between walls)
-    int nl;      // lines in the block
-    bool col;
+    int n;        // stored length of each line
+    int nl;       // lines in the block
+    bool col;     // column layout
+    bool mirror;  // even extension of length 2n (between walls)
     __device__ __forceinline__ int slot(int l, int j) const { return col ? j * nl + l : l * n + j; }
     // value at position j (any integer) of line l; par = parity of the quantity
     __device__ __forceinline__ double get(const double *buf, int l, int j, double par) const
     {
+        if (FAST) {
+            if (!mirror) {
+                j = j < 0 ? j + n : (j >= n ? j - n : j);
+                return buf[slot(l, j)];
+            }
+            if (j < 0) return par * buf[slot(l, -1 - j)];
+            if (j >= n) return par * buf[slot(l, 2 * n - 1 - j)];
+            return buf[slot(l, j)];
+        }
+        const int period = mirror ? 2 * n : n;
         int m = j % period;
         if (m < 0) m += period;
         if (m >= n) return par * buf[slot(l, period - 1 - m)];
@@ -123,13 +79,14 @@ struct Elems {
     bool ok[kElemsPerThread];
 };
 
-__device__ __forceinline__ Elems make_elems(const LineMap &m)
+template <bool FAST>
+__device__ __forceinline__ Elems make_elems(const LineMap<FAST> &m)
 {
     Elems E;
     const int total = m.n * m.nl;
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
-        int e = threadIdx.x + k * kBlockThreads;
+        int e = threadIdx.x + k * blockDim.x;
         E.e[k] = e;
         E.ok[k] = e < total;
         if (m.col) {
@@ -147,7 +104,9 @@ __device__ __forceinline__ Elems make_elems(const LineMap &m)
 // holds the input (parity par_in) for every element and is visible to the
 // whole block; `tmp` is scratch.  Returns the buffer holding the result
 // (parity -par_in); the calling thread's results are also left in out[].
-__device__ double *cfm_solve(const KParams &p, const LineMap &m, const Elems &E, double *in,
+template <bool FAST>
+__device__ __forceinline__ double *cfm_solve(const KParams &p, const LineMap<FAST> &m,
+                                             const Elems &E, double *in,
                              double *tmp, double par_in, double (&out)[kElemsPerThread])
 {
     const double par = -par_in;
@@ -169,7 +128,7 @@ __device__ double *cfm_solve(const KParams &p, const LineMap &m, const Elems &E,
         for (int k = 0; k < kElemsPerThread; ++k) {
             if (!E.ok[k]) continue;
             const int l = E.l[k], j = E.j[k];
-            double v = (src[E.e[k]] - c * (m.get(src, l, j - h, par) + m.get(src, l, j + h, par))) * g;
+            double v = (out[k] - c * (m.get(src, l, j - h, par) + m.get(src, l, j + h, par))) * g;
             dst[E.e[k]] = v;
             out[k] = v;
         }
@@ -181,17 +140,19 @@ __device__ double *cfm_solve(const KParams &p, const LineMap &m, const Elems &E,
     return src;
 }
 
-__global__ __launch_bounds__(kBlockThreads) void k_rows_rho(KParams p,
-                                                            const double *__restrict__ f,
-                                                            double *__restrict__ rho_out,
-                                                            double *__restrict__ dxx_out)
+template <bool FAST, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
+                                                               const double *__restrict__ f,
+                                                               double *__restrict__ rho_out,
+                                                               double *__restrict__ dxx_out)
 {
-    __shared__ double bA[kBlockElems], bB[kBlockElems];
+    extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
     const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
-    const LineMap m{nx, nx, rows, false};
+    double *bA = smem, *bB = smem + p.rows_per_block * nx;
+    const LineMap<FAST> m{nx, rows, false, false};
     const Elems E = make_elems(m);
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
@@ -215,17 +176,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_rho(KParams p,
     }
 }
 
-__global__ __launch_bounds__(kBlockThreads) void k_cols_mu(KParams p,
-                                                           const double *__restrict__ rho,
-                                                           const double *__restrict__ dxx,
-                                                           double *__restrict__ mu_out,
-                                                           double *__restrict__ fy_out)
+// Column strip handled by this block.  With col_xcd_groups = 8 the blocks are
+// renumbered so that consecutive strips (which share cache lines of every
+// row) are dispatched to the same XCD and meet in its L2.
+__device__ __forceinline__ int strip_of_block(const KParams &p)
 {
-    __shared__ double bA[kBlockElems], bB[kBlockElems];
+    const int b = blockIdx.x, g = p.col_xcd_groups;
+    if (g <= 1) return b;
+    const int per = gridDim.x / g;
+    return (b % g) * per + b / g;
+}
+
+template <bool FAST, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_cols_mu(KParams p,
+                                                              const double *__restrict__ rho,
+                                                              const double *__restrict__ dxx,
+                                                              double *__restrict__ mu_out,
+                                                              double *__restrict__ fy_out)
+{
+    extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
-    const int x0 = blockIdx.x * p.cols_per_block;
+    const int x0 = strip_of_block(p) * p.cols_per_block;
     const int cols = min(p.cols_per_block, nx - x0);
-    const LineMap m{ny, p.bc_y ? 2 * ny : ny, cols, true};
+    double *bA = smem, *bB = smem + p.cols_per_block * ny;
+    const LineMap<FAST> m{ny, cols, true, p.bc_y != 0};
     const Elems E = make_elems(m);
     double r[kElemsPerThread];
 #pragma unroll
@@ -257,25 +231,32 @@ __global__ __launch_bounds__(kBlockThreads) void k_cols_mu(KParams p,
     }
 }
 
-template <bool OBSERVE>
-__global__ __launch_bounds__(kBlockThreads) void k_rows_collide(
+// KEEP: hold the nine populations of each element in registers between the
+// first read and the collision (256-thread blocks); otherwise read them again.
+template <bool FAST, int MAXT, bool OBSERVE>
+__global__ __launch_bounds__(MAXT) void k_rows_collide(
     KParams p, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
     double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
 {
-    __shared__ double bA[kBlockElems], bB[kBlockElems];
+    extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
     const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
-    const LineMap m{nx, nx, rows, false};
+    double *bA = smem, *bB = smem + p.rows_per_block * nx;
+    const LineMap<FAST> m{nx, rows, false, false};
     const Elems E = make_elems(m);
+    constexpr bool KEEP = MAXT <= 256;
+    constexpr int NK = KEEP ? kElemsPerThread : 1;
+    double fi[NK][9], rho[kElemsPerThread];
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
-        double fi[9];
-        load9(f, N, (size_t)(y0 + E.l[k]) * nx + E.j[k], fi);
-        bA[E.e[k]] = sum9(fi);
+        double (&q)[9] = fi[KEEP ? k : 0];
+        load9(f, N, (size_t)(y0 + E.l[k]) * nx + E.j[k], q);
+        rho[k] = sum9(q);
+        bA[E.e[k]] = rho[k];
     }
     __syncthreads();
     double dxr[kElemsPerThread], dxm[kElemsPerThread];
@@ -288,33 +269,33 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_collide(
     __syncthreads();
     cfm_solve(p, m, E, bA, bB, 1.0, dxm);
 
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
         const int x = E.j[k], y = y0 + E.l[k];
         const size_t node = (size_t)y * nx + x;
-        double fi[9];
-        load9(f, N, node, fi);
-        const double rho = sum9(fi);
-        const double jx = (fi[1] - fi[3]) + (fi[5] - fi[6]) + (fi[8] - fi[7]);
-        const double jy = (fi[2] - fi[4]) + (fi[5] - fi[8]) + (fi[6] - fi[7]);
-        const double Fx = -rho * dxm[k] + CS2 * dxr[k];
+        double (&q)[9] = fi[KEEP ? k : 0];
+        if (!KEEP) load9(f, N, node, q);
+        const double rh = rho[k];
+        const double jx = (q[1] - q[3]) + (q[5] - q[6]) + (q[8] - q[7]);
+        const double jy = (q[2] - q[4]) + (q[5] - q[8]) + (q[6] - q[7]);
+        const double Fx = -rh * dxm[k] + CS2 * dxr[k];
         const double Fy = fy[node];
-        const double ux = jx / rho, uy = jy / rho;
+        const double ux = jx / rh, uy = jy / rh;
         if (OBSERVE) {
-            if (o_rho) o_rho[node] = rho;
-            if (o_vx) o_vx[node] = ux + Fx / (2.0 * rho);
-            if (o_vy) o_vy[node] = uy + Fy / (2.0 * rho);
+            if (o_rho) o_rho[node] = rh;
+            if (o_vx) o_vx[node] = ux + Fx / (2.0 * rh);
+            if (o_vy) o_vy[node] = uy + Fy / (2.0 * rh);
             if (o_fx) o_fx[node] = Fx;
             continue;
         }
-        const double vx2 = ux + Fx / rho, vy2 = uy + Fy / rho;
+        const double vx2 = ux + Fx / rh, vy2 = uy + Fy / rh;
         const double uu = ux * ux + uy * uy, uu2 = vx2 * vx2 + vy2 * vy2;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const double eq = feq(i, rho, ux, uy, uu);
-            const double eq2 = feq(i, rho, vx2, vy2, uu2);
-            const double fs = fi[i] - (fi[i] - eq) * p.inv_tau + (eq2 - eq);
+            const double eq = feq(i, rh, ux, uy, uu);
+            const double eq2 = feq(i, rh, vx2, vy2, uu2);
+            const double fs = q[i] - (q[i] - eq) * p.inv_tau + (eq2 - eq);
             int tx = x + EX[i];
             tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
             int ty = y + EY[i];
@@ -322,7 +303,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_collide(
                 if (p.bc_y) {
                     // half-way bounce-back; a moving wall adds -2 w rho (e.U)/c_s^2
                     const double eu = EX[i] * p.wall_ux;
-                    fout[OPP[i] * N + node] = fs - 2.0 * WT[i] * rho * eu / CS2;
+                    fout[OPP[i] * N + node] = fs - 2.0 * WT[i] * rh * eu / CS2;
                     continue;
                 }
                 ty = ty < 0 ? ty + ny : ty - ny;
@@ -331,7 +312,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_rows_collide(
         }
     }
 }
-
 __global__ void k_init_feq(KParams p, const double *__restrict__ rho0,
                            const double *__restrict__ ux0, const double *__restrict__ uy0,
                            double *__restrict__ f)
@@ -406,31 +386,109 @@ __global__ __launch_bounds__(kRedThreads) void k_fold_partials(const double *__r
     }
 }
 
+}  // namespace
+
 int row_blocks(const KParams &p) { return (p.ny + p.rows_per_block - 1) / p.rows_per_block; }
 int col_blocks(const KParams &p) { return (p.nx + p.cols_per_block - 1) / p.cols_per_block; }
 
-}  // namespace
+static int round_threads(int elems)
+{
+    int t = (elems + kElemsPerThread - 1) / kElemsPerThread;
+    t = (t + 63) / 64 * 64;
+    return t < 64 ? 64 : (t > kMaxBlockThreads ? kMaxBlockThreads : t);
+}
+
+// Chunks carried by the fast solve for a chunk length: the smallest M with
+// |q|^(M lc) < 2^-60, and q^lc.
+static void iir_carry(const KParams &p, int lc, int *M, double *qL)
+{
+    double ql = 1.0;
+    for (int k = 0; k < lc; ++k) ql *= p.iir_q;
+    int m = 1;
+    double t = std::fabs(ql);
+    while (t >= 0x1p-60 && m < 64) {
+        t *= std::fabs(ql);
+        ++m;
+    }
+    *M = m;
+    *qL = ql;
+}
+
+void set_row_shape(KParams *p)
+{
+    iir_carry(*p, kIirRowChunk, &p->iir_m_row, &p->iir_qL_row);
+    // one row per block for long rows, else as many whole rows as fill
+    // 1024 elements (256 threads)
+    const int R = p->nx >= 1024 ? 1 : 1024 / p->nx;
+    p->rows_per_block = R;
+    p->row_threads = round_threads(R * p->nx);
+    p->use_iir_rows = iir_rows_ok(*p);
+}
+
+void set_col_shape(KParams *p, int width, int chunk)
+{
+    int wmax = kMaxBlockElems / p->ny;
+    if (wmax < 1) wmax = 1;
+    int w = width < 1 ? 1 : (width > wmax ? wmax : width);
+    p->cols_per_block = w;
+    p->col_threads = round_threads(w * p->ny);
+    p->col_lc = chunk;
+    p->use_iir_cols = (chunk == 4 || chunk == 8 || chunk == 16) && iir_cols_ok(*p, chunk, w);
+    iir_carry(*p, chunk, &p->iir_m_col, &p->iir_qL_col);
+    const int nb = col_blocks(*p);
+    p->col_xcd_groups = (nb % 8 == 0 && nb >= 64 && p->nx % w == 0) ? 8 : 1;
+}
+
+static size_t row_lds(const KParams &p) { return 2 * sizeof(double) * p.rows_per_block * p.nx; }
+static size_t col_lds(const KParams &p) { return 2 * sizeof(double) * p.cols_per_block * p.ny; }
+static bool row_fast(const KParams &p) { return p.nx >= kFastMinLine; }
+static bool col_fast(const KParams &p) { return p.ny >= kFastMinLine; }
+
+// Launch kernel template K<FAST, MAXT, ...> with the instantiation matching
+// the line length (FAST) and block size (MAXT = 256 or 1024).
+#define CPLBM_DISPATCH(K, FASTC, THREADS, ...)                                   \
+    do {                                                                       \
+        if ((FASTC) && (THREADS) <= 256)                                       \
+            hipLaunchKernelGGL((K<true, 256 __VA_OPT__(,) __VA_ARGS__>), GRID); \
+        else if (FASTC)                                                        \
+            hipLaunchKernelGGL((K<true, 1024 __VA_OPT__(,) __VA_ARGS__>), GRID);\
+        else if ((THREADS) <= 256)                                             \
+            hipLaunchKernelGGL((K<false, 256 __VA_OPT__(,) __VA_ARGS__>), GRID);\
+        else                                                                   \
+            hipLaunchKernelGGL((K<false, 1024 __VA_OPT__(,) __VA_ARGS__>), GRID);\
+    } while (0)
 
 hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *dxx,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows_rho, dim3(row_blocks(p)), dim3(kBlockThreads), 0, s, p, f, rho, dxx);
+    if (p.use_iir_rows) return launch_rows_rho_iir(p, f, rho, dxx, s);
+#define GRID dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, rho, dxx
+    CPLBM_DISPATCH(k_rows_rho, row_fast(p), p.row_threads);
+#undef GRID
     return hipGetLastError();
 }
 
 hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *dxx, double *mu,
                           double *fy, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cols_mu, dim3(col_blocks(p)), dim3(kBlockThreads), 0, s, p, rho, dxx, mu,
-                       fy);
+    if (p.use_iir_cols) return launch_cols_mu_iir(p, rho, dxx, mu, fy, s);
+#define GRID dim3(col_blocks(p)), dim3(p.col_threads), col_lds(p), s, p, rho, dxx, mu, fy
+    CPLBM_DISPATCH(k_cols_mu, col_fast(p), p.col_threads);
+#undef GRID
     return hipGetLastError();
 }
 
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
                                const double *fy, double *fout, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows_collide<false>, dim3(row_blocks(p)), dim3(kBlockThreads), 0, s, p, f,
-                       mu, fy, fout, nullptr, nullptr, nullptr, nullptr);
+    if (p.use_iir_rows)
+        return launch_rows_collide_iir(p, f, mu, fy, fout, nullptr, nullptr, nullptr, nullptr,
+                                       false, s);
+#define GRID                                                                                 \
+    dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, mu, fy, fout, nullptr,    \
+        nullptr, nullptr, nullptr
+    CPLBM_DISPATCH(k_rows_collide, row_fast(p), p.row_threads, false);
+#undef GRID
     return hipGetLastError();
 }
 
@@ -438,8 +496,13 @@ hipError_t launch_rows_observe(const KParams &p, const double *f, const double *
                                const double *fy, double *rho, double *vx, double *vy,
                                double *fx, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rows_collide<true>, dim3(row_blocks(p)), dim3(kBlockThreads), 0, s, p, f,
-                       mu, fy, nullptr, rho, vx, vy, fx);
+    if (p.use_iir_rows)
+        return launch_rows_collide_iir(p, f, mu, fy, nullptr, rho, vx, vy, fx, true, s);
+#define GRID                                                                                 \
+    dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, mu, fy, nullptr, rho, vx, \
+        vy, fx
+    CPLBM_DISPATCH(k_rows_collide, row_fast(p), p.row_threads, true);
+#undef GRID
     return hipGetLastError();
 }
 

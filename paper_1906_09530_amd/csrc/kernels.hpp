@@ -5,23 +5,39 @@
 
 namespace cplbm {
 
-constexpr int kMaxStages = 8;      // parallel cyclic reduction stages
-constexpr int kBlockThreads = 1024;
-constexpr int kElemsPerThread = 4;
-constexpr int kBlockElems = kBlockThreads * kElemsPerThread;  // line elements per block (LDS)
+constexpr int kMaxStages = 8;        // parallel cyclic reduction stages
+constexpr int kElemsPerThread = 4;   // line elements held by one thread
+constexpr int kMaxBlockThreads = 1024;
+constexpr int kMaxBlockElems = kMaxBlockThreads * kElemsPerThread;  // 4096 doubles per LDS buffer
+constexpr int kFastMinLine = 64;     // lines this long skip the general modulo indexing
 
 // Everything a kernel needs, passed by value.
 struct KParams {
     int nx, ny, bc_y, eos;
-    int rows_per_block;  // row passes: whole rows per block
-    int cols_per_block;  // column pass: whole columns per block
-    int nstage;          // reduction stages of the line solve
-    int kappa_zero;      // kappa == 0: the Laplacian is not needed
+    // row passes: whole rows per block, threads per block
+    int rows_per_block, row_threads;
+    // column pass: whole columns per block, threads per block, and the
+    // block -> strip permutation that keeps neighbouring strips on one XCD
+    int cols_per_block, col_threads, col_xcd_groups;
+    int nstage;      // reduction stages of the line solve
+    int kappa_zero;  // kappa == 0: the Laplacian is not needed
     double a, b, RT, A;  // EOS constants; A = a alpha(T)
     double k2, kappa, inv_tau, mu_cap, wall_ux;
     double cfd_a2, cfd_b4;  // a/2 and b/4 of Eq. 37 (h = 1)
     double pcr_c[kMaxStages], pcr_g[kMaxStages];
+    // factorised inverse of the circulant compact-scheme matrix (fast path):
+    // pole q, 1/q, K = 1/(1 + 2 al q), powers q^0..q^16, and per pass the
+    // chunk length, its power q^LC and the number of carried chunks M
+    int use_iir_rows, use_iir_cols, col_lc;
+    int iir_m_row, iir_m_col;
+    double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
+    double iir_qp[17];
 };
+
+constexpr int kIirRowChunk = 4;
+
+int row_blocks(const KParams &p);
+int col_blocks(const KParams &p);
 
 // Pass A over rows: rho = sum f, d/dx rho, d2/dx2 rho.  Writes rho, dxx.
 hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *dxx,
@@ -45,5 +61,23 @@ hipError_t launch_init_feq(const KParams &p, const double *rho0, const double *u
 hipError_t launch_rho_delta(const KParams &p, const double *f, double *prev, double *partial,
                             int nblocks, double *out, hipStream_t s);
 int rho_delta_blocks(const KParams &p);
+
+// Block shapes for a mesh: rows per block, and columns per block for a
+// requested strip width (clamped to what one block's LDS holds) and chunk
+// length of the fast column solve (4, 8 or 16 nodes per thread).  Both pick
+// the factorised-inverse kernels whenever the line allows it.
+void set_row_shape(KParams *p);
+void set_col_shape(KParams *p, int width, int chunk);
+
+// Fast-path kernels (kernels_iir.hip) and their eligibility.
+bool iir_rows_ok(const KParams &p);
+bool iir_cols_ok(const KParams &p, int chunk, int width);
+hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *dxx,
+                               hipStream_t s);
+hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *dxx, double *mu,
+                              double *fy, hipStream_t s);
+hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,
+                                   const double *fy, double *fout, double *o_rho, double *o_vx,
+                                   double *o_vy, double *o_fx, bool observe, hipStream_t s);
 
 }  // namespace cplbm

@@ -1,0 +1,455 @@
+// Time-step kernels whose compact-scheme solves use the factorised inverse of
+// the circulant tridiagonal matrix (the fast path; kernels.hip holds the
+// general parallel-cyclic-reduction path used for short or ragged lines).
+//
+// Eq. 37 on a periodic line is C d = r with C = I + al (S + S^-1).  Writing
+// C = (1 + 2 al q)^-1 (I - q S)(I - q S^-1) / ... one finds, on an infinite
+// line, (C^-1)_ij = K q^|i-j| with q = (-1 + sqrt(1 - 4 al^2)) / (2 al) and
+// K = 1 / (1 + 2 al q); |q| = 0.382 (al = 1/3) or 0.268 (al = 1/4).  Hence
+//     d_i = K (y_i + z_i),  y_i = r_i + q y_{i-1},  z_i = q (r_{i+1} + z_{i+1}),
+// a causal and an anti-causal first-order recurrence.  On a periodic line of
+// n >= 64 nodes the wrap-around terms of the exact periodic inverse carry a
+// factor q^n < 1e-26 and are absorbed in the same recurrences run cyclically.
+//
+// Each thread owns LC consecutive nodes of one line (a chunk).  It runs both
+// recurrences over its chunk from zero, publishes the two partial sums
+//     P_c = sum_{m<LC} q^m r_{last-m},   B_c = sum_{m<LC} q^(m+1) r_{first+m},
+// and then adds the contributions of the M chunks before and after it,
+//     y_k += q^(k+1) sum_{m=1..M} q^((m-1)LC) P_{c-m},
+//     z_k += q^(LC-1-k) sum_{m=1..M} q^((m-1)LC) B_{c+m},
+// with M the smallest count for which |q|^(M LC) < 2^-60.  Two barriers per
+// solve.  Between walls the column is the even extension of length 2 ny:
+// a chunk beyond a wall is the mirror image of a physical chunk, whose P and B
+// swap roles (P of the image of chunk i is par B_i / q, B of the image is
+// par q P_i, par being the parity of the right-hand side).
+#include "kernels.hpp"
+#include "physics.hpp"
+
+namespace cplbm {
+
+namespace {
+
+using namespace phys;
+
+// The thread's chunk within the block's lines.
+template <int LC>
+struct Chunk {
+    int n;      // line length
+    int nc;     // chunks per line (n / LC)
+    int nl;     // lines held by the block (row or column count of the layout)
+    bool col;   // column layout: value slot j * nl + l, carry slot c * nl + l
+    bool mirror;
+    int l, c;   // this thread's line and chunk
+    bool ok;    // the line exists (ragged last block)
+    __device__ __forceinline__ int vslot(int j) const { return col ? j * nl + l : l * n + j; }
+    __device__ __forceinline__ int cslot(int ci) const { return col ? ci * nl + l : l * nc + ci; }
+};
+
+// First derivative of u (parity par_u) along the thread's line; the whole
+// block calls it together.  vbuf: n*nl doubles of LDS; cP, cB: nc*nl each.
+template <int LC>
+__device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, int M, double qL,
+                                          const double (&u)[LC], double par_u, double *vbuf,
+                                          double *cP, double *cB, double (&d)[LC])
+{
+    const int j0 = m.c * LC, n = m.n;
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) vbuf[m.vslot(j0 + k)] = u[k];
+    }
+    __syncthreads();
+    const double q = p.iir_q;
+    double r[LC], y[LC], z[LC];
+    double Pc = 0.0, Bc = 0.0;
+    if (m.ok) {
+        double um2, um1, up0, up1;  // u at j0-2, j0-1, j0+LC, j0+LC+1
+        if (!m.mirror) {
+            int a = j0 - 2, b = j0 - 1, e = j0 + LC, f = j0 + LC + 1;
+            a = a < 0 ? a + n : a;
+            b = b < 0 ? b + n : b;
+            e = e >= n ? e - n : e;
+            f = f >= n ? f - n : f;
+            um2 = vbuf[m.vslot(a)];
+            um1 = vbuf[m.vslot(b)];
+            up0 = vbuf[m.vslot(e)];
+            up1 = vbuf[m.vslot(f)];
+        } else {
+            um2 = j0 >= 2 ? vbuf[m.vslot(j0 - 2)] : par_u * u[1];
+            um1 = j0 >= 1 ? vbuf[m.vslot(j0 - 1)] : par_u * u[0];
+            up0 = j0 + LC < n ? vbuf[m.vslot(j0 + LC)] : par_u * u[LC - 1];
+            up1 = j0 + LC + 1 < n ? vbuf[m.vslot(j0 + LC + 1)] : par_u * u[LC - 2];
+        }
+        auto U = [&](int i) -> double {
+            return i == -2 ? um2 : i == -1 ? um1 : i == LC ? up0 : i == LC + 1 ? up1 : u[i];
+        };
+#pragma unroll
+        for (int k = 0; k < LC; ++k)
+            r[k] = p.cfd_a2 * (U(k + 1) - U(k - 1)) + p.cfd_b4 * (U(k + 2) - U(k - 2));
+        y[0] = r[0];
+#pragma unroll
+        for (int k = 1; k < LC; ++k) y[k] = r[k] + q * y[k - 1];
+        z[LC - 1] = 0.0;
+#pragma unroll
+        for (int k = LC - 2; k >= 0; --k) z[k] = q * (r[k + 1] + z[k + 1]);
+        Pc = y[LC - 1];
+        Bc = q * (r[0] + z[0]);
+        cP[m.cslot(m.c)] = Pc;
+        cB[m.cslot(m.c)] = Bc;
+    }
+    __syncthreads();
+    if (!m.ok) return;
+    const double par_r = -par_u;
+    const int nc = m.nc;
+    double Yc = 0.0, Zc = 0.0;
+    for (int mm = M; mm >= 1; --mm) {
+        int a = m.c - mm, b = m.c + mm;
+        double pa, bb;
+        if (!m.mirror) {
+            a = a < 0 ? a + nc : a;
+            b = b >= nc ? b - nc : b;
+            pa = cP[m.cslot(a)];
+            bb = cB[m.cslot(b)];
+        } else {
+            pa = a >= 0 ? cP[m.cslot(a)] : par_r * p.iir_inv_q * cB[m.cslot(-1 - a)];
+            bb = b < nc ? cB[m.cslot(b)] : par_r * q * cP[m.cslot(2 * nc - 1 - b)];
+        }
+        Yc = Yc * qL + pa;
+        Zc = Zc * qL + bb;
+    }
+#pragma unroll
+    for (int k = 0; k < LC; ++k)
+        d[k] = p.iir_K * ((y[k] + p.iir_qp[k + 1] * Yc) + (z[k] + p.iir_qp[LC - 1 - k] * Zc));
+}
+
+// 16-byte vector access to LC consecutive doubles (32-byte aligned).
+template <int LC>
+__device__ __forceinline__ void vload(const double *__restrict__ src, double (&v)[LC])
+{
+#pragma unroll
+    for (int k = 0; k < LC; k += 2) {
+        const double2 t = *reinterpret_cast<const double2 *>(src + k);
+        v[k] = t.x;
+        v[k + 1] = t.y;
+    }
+}
+
+template <int LC>
+__device__ __forceinline__ void vstore(double *__restrict__ dst, const double (&v)[LC])
+{
+#pragma unroll
+    for (int k = 0; k < LC; k += 2) *reinterpret_cast<double2 *>(dst + k) = make_double2(v[k], v[k + 1]);
+}
+
+// Row chunk of this thread: rows_per_block lines of nx, nc = nx / LC chunks each.
+template <int LC>
+__device__ __forceinline__ Chunk<LC> row_chunk(const KParams &p, int rows)
+{
+    Chunk<LC> m;
+    m.n = p.nx;
+    m.nc = p.nx / LC;
+    m.nl = p.rows_per_block;
+    m.col = false;
+    m.mirror = false;
+    m.l = threadIdx.x / m.nc;
+    m.c = threadIdx.x - m.l * m.nc;
+    m.ok = m.l < rows;
+    return m;
+}
+
+constexpr int kRowLC = 4;
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ f,
+                                                       double *__restrict__ rho_out,
+                                                       double *__restrict__ dxx_out)
+{
+    constexpr int LC = kRowLC;
+    extern __shared__ double smem[];
+    const int nx = p.nx, ny = p.ny;
+    const size_t N = (size_t)nx * ny;
+    const int y0 = blockIdx.x * p.rows_per_block;
+    const int rows = min(p.rows_per_block, ny - y0);
+    const Chunk<LC> m = row_chunk<LC>(p, rows);
+    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
+    const size_t base = (size_t)(y0 + m.l) * nx + m.c * LC;
+    double rho[LC];
+    if (m.ok) {
+        double acc[LC];
+        vload<LC>(f + base, acc);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            double t[LC];
+            vload<LC>(f + i * N + base, t);
+#pragma unroll
+            for (int k = 0; k < LC; ++k) acc[k] += t[k];
+        }
+#pragma unroll
+        for (int k = 0; k < LC; ++k) rho[k] = acc[k];
+        vstore<LC>(rho_out + base, rho);
+    }
+    if (p.kappa_zero) return;  // uniform: the Laplacian is not used
+    double d1[LC], d2[LC];
+    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, d1);
+    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, d1, -1.0, vbuf, cP, cB, d2);
+    if (m.ok) vstore<LC>(dxx_out + base, d2);
+}
+
+template <int LC>
+__device__ __forceinline__ int strip_of_block(const KParams &p)
+{
+    const int b = blockIdx.x, g = p.col_xcd_groups;
+    if (g <= 1) return b;
+    const int per = gridDim.x / g;
+    return (b % g) * per + b / g;
+}
+
+template <int LC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *__restrict__ rho,
+                                                      const double *__restrict__ dxx,
+                                                      double *__restrict__ mu_out,
+                                                      double *__restrict__ fy_out)
+{
+    extern __shared__ double smem[];
+    const int nx = p.nx, ny = p.ny, W = p.cols_per_block;
+    const int x0 = strip_of_block<LC>(p) * W;
+    const int cols = min(W, nx - x0);
+    Chunk<LC> m;
+    m.n = ny;
+    m.nc = ny / LC;
+    m.nl = W;
+    m.col = true;
+    m.mirror = p.bc_y != 0;
+    m.c = threadIdx.x / W;
+    m.l = threadIdx.x - m.c * W;
+    m.ok = m.l < cols;
+    double *vbuf = smem, *cP = smem + W * ny, *cB = cP + W * m.nc;
+    const size_t col = x0 + m.l;
+    const int j0 = m.c * LC;
+    double r[LC];
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) r[k] = rho[(size_t)(j0 + k) * nx + col];
+    }
+    double dyr[LC], dyy[LC], mu[LC], dym[LC];
+    iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, r, 1.0, vbuf, cP, cB, dyr);
+    if (!p.kappa_zero) iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, dyr, -1.0, vbuf, cP, cB, dyy);
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            const size_t node = (size_t)(j0 + k) * nx + col;
+            double v = p.k2 * mu0_capped(p, r[k]);
+            if (!p.kappa_zero) v -= p.kappa * (dxx[node] + dyy[k]);
+            mu[k] = v;
+            mu_out[node] = v;
+        }
+    }
+    iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, mu, 1.0, vbuf, cP, cB, dym);
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k)
+            fy_out[(size_t)(j0 + k) * nx + col] = -r[k] * dym[k] + CS2 * dyr[k];
+    }
+}
+
+template <int MAXT, bool OBSERVE>
+__global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
+    KParams p, const double *__restrict__ f, const double *__restrict__ mu,
+    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
+    double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
+{
+    constexpr int LC = kRowLC;
+    extern __shared__ double smem[];
+    const int nx = p.nx, ny = p.ny;
+    const size_t N = (size_t)nx * ny;
+    const int y0 = blockIdx.x * p.rows_per_block;
+    const int rows = min(p.rows_per_block, ny - y0);
+    const Chunk<LC> m = row_chunk<LC>(p, rows);
+    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
+    const int y = y0 + m.l, x0 = m.c * LC;
+    const size_t base = (size_t)y * nx + x0;
+    // KEEP: the nine populations stay in registers from the first read to the
+    // collision (256-thread blocks); otherwise each is read again when needed.
+    constexpr bool KEEP = MAXT <= 256;
+    constexpr int NI = KEEP ? 9 : 1;
+    double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
+    if (m.ok) {
+        // rho = f0 + f1 + ... + f8 in index order; momentum in opposite pairs,
+        // jx = (f1 - f3) + (f5 - f6) + (f8 - f7), jy = (f2 - f4) + (f5 - f8) +
+        // (f6 - f7), formed as the planes arrive
+        double t1[LC], t2[LC], t5[LC], t6[LC], t7[LC], dx1[LC], dx2[LC], dy1[LC];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            double t[LC];
+            vload<LC>(f + i * N + base, t);
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                if (KEEP) fi[i][k] = t[k];
+                rho[k] = i == 0 ? t[k] : rho[k] + t[k];
+                switch (i) {
+                case 1: t1[k] = t[k]; break;
+                case 2: t2[k] = t[k]; break;
+                case 3: dx1[k] = t1[k] - t[k]; break;
+                case 4: dy1[k] = t2[k] - t[k]; break;
+                case 5: t5[k] = t[k]; break;
+                case 6: dx2[k] = t5[k] - t[k]; t6[k] = t[k]; break;
+                case 7: t7[k] = t[k]; break;
+                case 8:
+                    jx[k] = (dx1[k] + dx2[k]) + (t[k] - t7[k]);
+                    jy[k] = (dy1[k] + (t5[k] - t[k])) + (t6[k] - t7[k]);
+                    break;
+                default: break;
+                }
+            }
+        }
+        vload<LC>(mu + base, mv);
+    }
+    double dxr[LC], dxm[LC];
+    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, dxr);
+    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, mv, 1.0, vbuf, cP, cB, dxm);
+    if (!m.ok) return;
+    double Fy[LC];
+    vload<LC>(fy + base, Fy);
+    double ux[LC], uy[LC], vx2[LC], vy2[LC], uu[LC], uu2[LC];
+#pragma unroll
+    for (int k = 0; k < LC; ++k) {
+        const double rh = rho[k];
+        const double Fx = -rh * dxm[k] + CS2 * dxr[k];
+        ux[k] = jx[k] / rh;
+        uy[k] = jy[k] / rh;
+        if (OBSERVE) {
+            const size_t node = base + k;
+            if (o_rho) o_rho[node] = rh;
+            if (o_vx) o_vx[node] = ux[k] + Fx / (2.0 * rh);
+            if (o_vy) o_vy[node] = uy[k] + Fy[k] / (2.0 * rh);
+            if (o_fx) o_fx[node] = Fx;
+            continue;
+        }
+        vx2[k] = ux[k] + Fx / rh;
+        vy2[k] = uy[k] + Fy[k] / rh;
+        uu[k] = ux[k] * ux[k] + uy[k] * uy[k];
+        uu2[k] = vx2[k] * vx2[k] + vy2[k] * vy2[k];
+    }
+    if (OBSERVE) return;
+    // collision and push streaming, one population at a time: population i
+    // of node (x, y) goes to (x + e_x, y + e_y)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        double q[LC], v[LC];
+        if (KEEP) {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) q[k] = fi[KEEP ? i : 0][k];
+        } else {
+            vload<LC>(f + i * N + base, q);
+        }
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            const double eq = feq(i, rho[k], ux[k], uy[k], uu[k]);
+            const double eq2 = feq(i, rho[k], vx2[k], vy2[k], uu2[k]);
+            v[k] = q[k] - (q[k] - eq) * p.inv_tau + (eq2 - eq);
+        }
+        int ty = y + EY[i];
+        if (ty < 0 || ty >= ny) {
+            if (p.bc_y) {
+                // half-way bounce-back into the opposite population of the
+                // same node; a moving wall adds -2 w rho (e.U)/c_s^2
+#pragma unroll
+                for (int k = 0; k < LC; ++k)
+                    v[k] = v[k] - 2.0 * WT[i] * rho[k] * (EX[i] * p.wall_ux) / CS2;
+                vstore<LC>(fout + OPP[i] * N + base, v);
+                continue;
+            }
+            ty = ty < 0 ? ty + ny : ty - ny;
+        }
+        double *dst = fout + i * N + (size_t)ty * nx;
+        if (EX[i] == 0) {
+            vstore<LC>(dst + x0, v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                int tx = x0 + k + EX[i];
+                tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
+                dst[tx] = v[k];
+            }
+        }
+    }
+}
+
+}  // namespace
+
+bool iir_rows_ok(const KParams &p)
+{
+    return p.nx >= kFastMinLine && p.nx % kRowLC == 0 &&
+           p.rows_per_block * (p.nx / kRowLC) <= kMaxBlockThreads;
+}
+
+bool iir_cols_ok(const KParams &p, int lc, int width)
+{
+    return p.ny >= kFastMinLine && p.ny % lc == 0 && width * (p.ny / lc) <= kMaxBlockThreads &&
+           width * p.ny <= kMaxBlockElems;
+}
+
+static size_t row_lds_iir(const KParams &p)
+{
+    const size_t R = p.rows_per_block;
+    return sizeof(double) * (R * p.nx + 2 * R * (p.nx / kRowLC));
+}
+
+static size_t col_lds_iir(const KParams &p)
+{
+    const size_t W = p.cols_per_block;
+    return sizeof(double) * (W * p.ny + 2 * W * (p.ny / p.col_lc));
+}
+
+static int row_threads_iir(const KParams &p) { return p.rows_per_block * (p.nx / kRowLC); }
+static int col_threads_iir(const KParams &p) { return p.cols_per_block * (p.ny / p.col_lc); }
+
+#define CPLBM_IIR_THREADS(T, K256, K1024, GRIDARGS)                                       \
+    do {                                                                                   \
+        if ((T) <= 256)                                                                    \
+            hipLaunchKernelGGL(K256, GRIDARGS);                                            \
+        else                                                                               \
+            hipLaunchKernelGGL(K1024, GRIDARGS);                                           \
+    } while (0)
+
+hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *dxx,
+                               hipStream_t s)
+{
+    const int T = row_threads_iir(p);
+#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, rho, dxx
+    CPLBM_IIR_THREADS(T, k_rows_rho_iir<256>, k_rows_rho_iir<1024>, ARGS);
+#undef ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *dxx, double *mu,
+                              double *fy, hipStream_t s)
+{
+    const int T = col_threads_iir(p);
+#define ARGS dim3(col_blocks(p)), dim3(T), col_lds_iir(p), s, p, rho, dxx, mu, fy
+    switch (p.col_lc) {
+    case 4: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<4, 256>), (k_cols_mu_iir<4, 1024>), ARGS); break;
+    case 8: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<8, 256>), (k_cols_mu_iir<8, 1024>), ARGS); break;
+    default: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<16, 256>), (k_cols_mu_iir<16, 1024>), ARGS); break;
+    }
+#undef ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,
+                                   const double *fy, double *fout, double *o_rho, double *o_vx,
+                                   double *o_vy, double *o_fx, bool observe, hipStream_t s)
+{
+    const int T = row_threads_iir(p);
+#define ARGS                                                                                   \
+    dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, mu, fy, fout, o_rho, o_vx, o_vy, o_fx
+    if (observe)
+        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, true>), (k_rows_collide_iir<1024, true>),
+                          ARGS);
+    else
+        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, false>), (k_rows_collide_iir<1024, false>),
+                          ARGS);
+#undef ARGS
+    return hipGetLastError();
+}
+
+}  // namespace cplbm

@@ -1,0 +1,76 @@
+// Pointwise physics shared by the kernels: D2Q9 lattice, moments, the
+// equilibrium and the bounded bulk chemical potential (arXiv:1906.09530).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cplbm {
+namespace phys {
+
+// D2Q9 (Sec. 2)
+constexpr int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                                     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+constexpr double CS2 = 1.0 / 3.0;
+
+// rho = sum f_i in a fixed order (every pass computes it the same way).
+__device__ __forceinline__ double sum9(const double (&fi)[9])
+{
+    double r = fi[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) r += fi[i];
+    return r;
+}
+
+__device__ __forceinline__ void load9(const double *__restrict__ f, size_t N, size_t node,
+                                      double (&fi)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fi[i] = f[i * N + node];
+}
+
+// Equilibrium of Eq. 2 with c_s^2 = 1/3.
+__device__ __forceinline__ double feq(int i, double rho, double ux, double uy, double uu)
+{
+    const double eu = EX[i] * ux + EY[i] * uy;
+    return WT[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+// psi'(rho) of Eqs. 15, 17, 19, 21, bounded by the upper limit (Sec. 5.6):
+// outside the EOS domain, or when the formula gives NaN, the limit is used.
+__device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
+{
+    const double b = p.b, RT = p.RT, A = p.A;
+    const bool outside = (p.eos == 4) ? (b * rho * 0.25 >= 1.0) : (b * rho >= 1.0);
+    if (outside) return p.mu_cap;
+    double m;
+    switch (p.eos) {
+    case 0:  // van der Waals
+        m = RT * (log(rho / (1.0 - b * rho)) + 1.0 / (1.0 - b * rho)) - 2.0 * p.a * rho;
+        break;
+    case 1:
+    case 2:  // Redlich-Kwong, Soave-Redlich-Kwong
+        m = RT * log(rho / (1.0 - b * rho)) + RT / (1.0 - b * rho) - A / b * log(1.0 + b * rho) -
+            A * rho / (1.0 + b * rho);
+        break;
+    case 3: {  // Peng-Robinson
+        const double s2 = 1.4142135623730950488;
+        m = RT * log(rho / (1.0 - b * rho)) -
+            A / (2.0 * s2 * b) * log((s2 - 1.0 + b * rho) / (s2 + 1.0 - b * rho)) +
+            RT / (1.0 - b * rho) - A * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+        break;
+    }
+    default: {  // Carnahan-Starling
+        const double eta = b * rho * 0.25, q = 1.0 - eta;
+        m = RT * ((3.0 - eta) / (q * q * q) + log(rho) + 1.0) - 2.0 * p.a * rho;
+        break;
+    }
+    }
+    if (isnan(m)) return p.mu_cap;
+    return m < p.mu_cap ? m : p.mu_cap;
+}
+
+}  // namespace phys
+}  // namespace cplbm

@@ -77,6 +77,9 @@ def load():
         "lbm_get_state": (i32, [P, P, i32]),
         "lbm_set_state": (i32, [P, P, i32]),
         "lbm_time_passes": (i32, [P, i64, pd]),
+        "lbm_autotune": (i32, [P, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), pd,
+                            C.POINTER(C.c_int)]),
+        "lbm_set_column_shape": (i32, [P, i32, i32]),
         "lbm_steps_taken": (i64, [P]),
         "lbm_synchronize": (i32, [P]),
         "lbm_destroy": (None, [P]),
@@ -204,6 +207,19 @@ class Solver:
         out = (C.c_double * 3)()
         _check(load().lbm_time_passes(self.ctx, int(n), out), self.ctx)
         return list(out)
+
+    def autotune(self, repeats=20):
+        """Pick the fastest column-pass shape; returns {(width, chunk): ms}
+        (chunk 0: the general reduction kernel)."""
+        w = (C.c_int * 16)()
+        ch = (C.c_int * 16)()
+        ms = (C.c_double * 16)()
+        n = C.c_int()
+        _check(load().lbm_autotune(self.ctx, int(repeats), w, ch, ms, C.byref(n)), self.ctx)
+        return {(w[i], ch[i]): ms[i] for i in range(n.value)}
+
+    def set_column_shape(self, width, chunk):
+        _check(load().lbm_set_column_shape(self.ctx, int(width), int(chunk)), self.ctx)
 
     def get_state(self, device=False):
         if device:

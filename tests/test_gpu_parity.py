@@ -95,6 +95,54 @@ def test_ragged_tiles_pr_drop_with_limit():
     _run_case("pr300x200", p, op, rho0, ux0, uy0, [100, 300])
 
 
+@pytest.mark.parametrize("walls", [0, 1])
+def test_general_reduction_path(walls):
+    """98 x 66: lines of >= 64 nodes that are not multiples of 4 take the
+    general parallel-cyclic-reduction kernels in both directions."""
+    nx, ny = 98, 66
+    p, op = _case_params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0,
+                         bc_y=walls)
+    g, l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 18.0, 5.0, seed=11, noise=1e-6)
+    _run_case("general98x66-walls%d" % walls, p, op, rho0, ux0, uy0, [50, 200])
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_every_column_shape_matches_oracle(walls):
+    """Every column-pass shape the autotuner may pick (strip width x chunk
+    length, chunk 0 = general reduction kernel) gives mu and F within 1e-12
+    of the oracle on the same state; the tuned choice too."""
+    nx, ny = 128, 256
+    p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                         bc_y=walls)
+    g, l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 30.0, 4.0, seed=12, noise=1e-4,
+                                    center=(60.0, 120.0))
+    f = oracle.init(op, rho0, ux0, uy0)
+    _, _, _, mu2, fx2, fy2 = oracle.moments(op, f, want_force=True)
+    fm = max(np.abs(fx2).max(), np.abs(fy2).max())
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    shapes = [(w, c) for w in (1, 2, 4, 8, 16) for c in (0, 4, 8, 16)]
+    tried = 0
+    for w, c in shapes:
+        try:
+            s.set_column_shape(w, c)
+        except lbm.LBMError:
+            continue
+        tried += 1
+        mu, fx, fy = s.force_fields()
+        print("shape w=%d chunk=%d: mu %.2e F %.2e" % (
+            w, c, np.abs(mu - mu2).max() / np.abs(mu2).max(), np.abs(fy - fy2).max() / fm))
+        assert np.abs(mu - mu2).max() <= 1e-12 * np.abs(mu2).max()
+        assert np.abs(fy - fy2).max() <= 1e-12 * fm
+        assert np.abs(fx - fx2).max() <= 1e-12 * fm
+    assert tried >= 10
+    table = s.autotune(3)
+    assert len(table) >= 10
+    mu, fx, fy = s.force_fields()
+    assert np.abs(fy - fy2).max() <= 1e-12 * fm
+
+
 @pytest.mark.parametrize("frame", [0.0, 0.02])
 def test_walls_splash_moving_frame(frame):
     """Drop falling on a film between bounce-back walls (CS, T_r = 0.6),
