@@ -37,6 +37,32 @@ NX = NY = 1024
 CFG = dict(T_r=0.5, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0, radius=200.0, width=10.0)
 
 
+KERNEL_SOURCES = ["kernels.hip", "kernels_iir.hip", "kernels.hpp", "physics.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_pr1024.json")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1906_09530_amd", "csrc", s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return t["bytes_per_launch"].get(kernel)
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -140,6 +166,7 @@ def main():
     steps_total = s.steps_taken
     s.close()
 
+    traffic = measured_traffic(PASS_NAMES[dom])
     cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, ux0, uy0)
     out = {
         "metric": METRIC,
@@ -168,7 +195,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(gbs[dom] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes/launch",
+            "traffic_vs_algorithmic": (None if traffic is None else
+                                       round(traffic / (PASS_BYTES[dom] * NX * NY), 4)),
             "bytes_per_node": PASS_BYTES[dom],
             "avg_ms": round(pass_ms[dom], 6),
         },

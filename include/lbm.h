@@ -146,21 +146,25 @@ lbm_status lbm_run_until_converged(lbm_ctx *ctx, double tol, int64_t check_every
 lbm_status lbm_get_state(lbm_ctx *ctx, double *f, int dst_on_device);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
 
-/* Diagnostic: enqueue nsteps steps exactly like lbm_step, with a HIP event
- * recorded on the context's stream before and after every kernel, and
- * return the average device time of each pass in milliseconds:
- * ms_per_pass[0] = row pass (rho, d2/dx2 rho), [1] = column pass (mu, F_y),
- * [2] = row pass (F_x, collision, streaming).  Synchronises the stream. */
+/* Diagnostic: average device time in milliseconds of each kernel of a step
+ * on the current state, each launched nsteps times back to back between two
+ * HIP events on the context's stream: ms_per_pass[0] = row pass (rho,
+ * d2/dx2 rho), [1] = column pass (mu, F_y), [2] = row pass (F_x,
+ * collision, streaming into the spare buffer).  The state and the step
+ * count are not changed.  Synchronises the stream. */
 lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
 
 /* Autotuner: time the column pass of the current state for each strip width
  * (columns per workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS
  * holds and, for the factorised solve, each chunk length (column nodes per
- * thread) in {4, 8, 16}; `repeats` launches each (HIP events); keep the
- * fastest for the context.  The state f is not changed.  widths[],
- * chunks[] and ms[] (room for 15 entries each, may be NULL) receive the
- * candidates (chunk 0: general reduction kernel) and their average time in
- * milliseconds; *count (may be NULL) their number.  Synchronises. */
+ * thread) in {4, 8, 16}; then time the collision pass holding the nine
+ * populations in registers or reading them twice.  `repeats` launches each
+ * (HIP events); keep the fastest of each for the context.  The state f is
+ * not changed.  widths[], chunks[] and ms[] (room for 17 entries each, may be
+ * NULL) receive the candidates and their average time in milliseconds --
+ * column candidates as (width, chunk; chunk 0 = general reduction kernel),
+ * collision candidates as (0, 1 = registers / 0 = read twice) -- and *count
+ * (may be NULL) their number.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, double *ms,
                         int *count);
 

@@ -130,7 +130,12 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     k.a = p->a;
     k.b = p->b;
     k.RT = (double)((long double)p->R * T);
-    k.A = (double)((long double)p->a * eos_alpha(e, T, Tc));
+    const long double A = (long double)p->a * eos_alpha(e, T, Tc);
+    k.A = (double)A;
+    if (p->eos == LBM_EOS_PR)
+        k.eos_c1 = (double)(A / (2.0L * sqrtl(2.0L) * (long double)p->b));
+    else
+        k.eos_c1 = (double)(A / (long double)p->b);
     k.k2 = p->k * p->k;
     k.kappa = p->kappa;
     k.inv_tau = 1.0 / p->tau;
@@ -165,6 +170,7 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
         qp *= q;
     }
     set_row_shape(&k);
+    k.row_keep = 1;
     set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
     *kp = k;
     return true;
@@ -492,45 +498,35 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
     if (nsteps <= 0 || !ms_per_pass) return fail(c, LBM_E_INVALID, "nsteps > 0 and an output required");
-    constexpr int kChunk = 256;
-    std::vector<hipEvent_t> ev(4 * kChunk, nullptr);
-    for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto &q : ev)
-                if (q) (void)hipEventDestroy(q);
-            return fail(c, LBM_E_DEVICE, "hipEventCreate failed");
+    // Each pass is idempotent on the state: passes A and B rewrite the same
+    // scalar planes from the same inputs and pass C writes only the spare
+    // distribution buffer.  So each is timed over nsteps back-to-back launches
+    // between two events, which keeps per-launch event overhead out of the
+    // average.
+    hipEvent_t e0, e1;
+    HIP_OR(c, hipEventCreate(&e0));
+    HIP_OR(c, hipEventCreate(&e1));
+    const double *fc = c->f[c->cur];
+    double *fn = c->f[1 - c->cur];
+    hipError_t err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
+    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+    for (int q = 0; q < 3 && err == hipSuccess; ++q) {
+        err = hipEventRecord(e0, c->stream);
+        for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
+            if (q == 0) err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
+            if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+            if (q == 2) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream);
         }
-    double acc[3] = {0, 0, 0};
-    hipError_t err = hipSuccess;
-    for (int64_t done = 0; done < nsteps && err == hipSuccess;) {
-        const int n = (int)std::min<int64_t>(kChunk, nsteps - done);
-        for (int s = 0; s < n && err == hipSuccess; ++s) {
-            const double *fc = c->f[c->cur];
-            double *fn = c->f[1 - c->cur];
-            hipEvent_t *e = &ev[4 * s];
-            if (err == hipSuccess) err = hipEventRecord(e[0], c->stream);
-            if (err == hipSuccess) err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[1], c->stream);
-            if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[2], c->stream);
-            if (err == hipSuccess) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
-            c->cur = 1 - c->cur;
-            c->steps += 1;
-        }
-        if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
-        for (int s = 0; s < n && err == hipSuccess; ++s)
-            for (int q = 0; q < 3 && err == hipSuccess; ++q) {
-                float ms = 0.f;
-                err = hipEventElapsedTime(&ms, ev[4 * s + q], ev[4 * s + q + 1]);
-                acc[q] += ms;
-            }
-        done += n;
+        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        ms_per_pass[q] = ms / (double)nsteps;
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (err != hipSuccess)
         return fail(c, LBM_E_DEVICE, std::string("pass timing failed: ") + hipGetErrorString(err));
-    for (int q = 0; q < 3; ++q) ms_per_pass[q] = acc[q] / (double)nsteps;
     return LBM_OK;
 }
 
@@ -578,11 +574,42 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
             best_c = ch;
         }
     }
+    if (err == hipSuccess) set_col_shape(&c->kp, best_w, best_c);
+    // collision pass: populations held in registers or read twice.  It reads
+    // the current f, mu and F_y and writes only the spare buffer, so the state
+    // is untouched; mu and F_y are refreshed first with the chosen shape.
+    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+    double best_row = INFINITY;
+    int best_keep = c->kp.row_keep;
+    for (int keep = 0; keep < 2 && err == hipSuccess; ++keep) {
+        KParams kp = c->kp;
+        kp.row_keep = keep;
+        const double *fc = c->f[c->cur];
+        double *fn = c->f[1 - c->cur];
+        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+        for (int r = 0; r < repeats && err == hipSuccess; ++r)
+            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) break;
+        const double avg = t / repeats;
+        if (widths) widths[n] = 0;
+        if (chunks) chunks[n] = keep;
+        if (ms) ms[n] = avg;
+        ++n;
+        if (avg < best_row) {
+            best_row = avg;
+            best_keep = keep;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess)
         return fail(c, LBM_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(err));
-    set_col_shape(&c->kp, best_w, best_c);
+    c->kp.row_keep = best_keep;
     if (count) *count = n;
     return LBM_OK;
 }

@@ -22,6 +22,7 @@ struct KParams {
     int nstage;      // reduction stages of the line solve
     int kappa_zero;  // kappa == 0: the Laplacian is not needed
     double a, b, RT, A;  // EOS constants; A = a alpha(T)
+    double eos_c1;       // A / b (RK, RKS) or A / (2 sqrt(2) b) (PR)
     double k2, kappa, inv_tau, mu_cap, wall_ux;
     double cfd_a2, cfd_b4;  // a/2 and b/4 of Eq. 37 (h = 1)
     double pcr_c[kMaxStages], pcr_g[kMaxStages];
@@ -29,6 +30,7 @@ struct KParams {
     // pole q, 1/q, K = 1/(1 + 2 al q), powers q^0..q^16, and per pass the
     // chunk length, its power q^LC and the number of carried chunks M
     int use_iir_rows, use_iir_cols, col_lc;
+    int row_keep;  // collision pass holds f in registers (tuned)
     int iir_m_row, iir_m_col;
     double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
     double iir_qp[17];

@@ -251,7 +251,10 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
     }
 }
 
-template <int MAXT, bool OBSERVE>
+// KEEP: the nine populations stay in registers from the first read to the
+// collision; otherwise each is read again when needed (fewer registers, so
+// more waves per SIMD; the second read is served by the caches).
+template <int MAXT, bool OBSERVE, bool KEEP>
 __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     KParams p, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
@@ -267,9 +270,6 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
     const int y = y0 + m.l, x0 = m.c * LC;
     const size_t base = (size_t)y * nx + x0;
-    // KEEP: the nine populations stay in registers from the first read to the
-    // collision (256-thread blocks); otherwise each is read again when needed.
-    constexpr bool KEEP = MAXT <= 256;
     constexpr int NI = KEEP ? 9 : 1;
     double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
     if (m.ok) {
@@ -312,20 +312,20 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     double ux[LC], uy[LC], vx2[LC], vy2[LC], uu[LC], uu2[LC];
 #pragma unroll
     for (int k = 0; k < LC; ++k) {
-        const double rh = rho[k];
+        const double rh = rho[k], ir = 1.0 / rh;
         const double Fx = -rh * dxm[k] + CS2 * dxr[k];
-        ux[k] = jx[k] / rh;
-        uy[k] = jy[k] / rh;
+        ux[k] = jx[k] * ir;
+        uy[k] = jy[k] * ir;
         if (OBSERVE) {
             const size_t node = base + k;
             if (o_rho) o_rho[node] = rh;
-            if (o_vx) o_vx[node] = ux[k] + Fx / (2.0 * rh);
-            if (o_vy) o_vy[node] = uy[k] + Fy[k] / (2.0 * rh);
+            if (o_vx) o_vx[node] = ux[k] + 0.5 * Fx * ir;
+            if (o_vy) o_vy[node] = uy[k] + 0.5 * Fy[k] * ir;
             if (o_fx) o_fx[node] = Fx;
             continue;
         }
-        vx2[k] = ux[k] + Fx / rh;
-        vy2[k] = uy[k] + Fy[k] / rh;
+        vx2[k] = ux[k] + Fx * ir;
+        vy2[k] = uy[k] + Fy[k] * ir;
         uu[k] = ux[k] * ux[k] + uy[k] * uy[k];
         uu2[k] = vx2[k] * vx2[k] + vy2[k] * vy2[k];
     }
@@ -363,12 +363,50 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
         double *dst = fout + i * N + (size_t)ty * nx;
         if (EX[i] == 0) {
             vstore<LC>(dst + x0, v);
-        } else {
+            continue;
+        }
+        // Shifted populations: the aligned chunk [x0, x0 + LC) of the target
+        // row receives LC - 1 of this thread's values and one value of the
+        // neighbouring chunk, taken from the adjacent lane.  Where that chunk
+        // is not on the adjacent lane (first/last lane of the wave, first/last
+        // chunk of the row), the boundary value goes out as a single store
+        // from its owner instead.
+        const int lane = threadIdx.x & 63;
+        if (EX[i] > 0) {
+            const double from_left = __shfl_up(v[LC - 1], 1);
+            const bool left_here = lane > 0 && m.c > 0;
+            double w[LC];
+            w[0] = from_left;
 #pragma unroll
-            for (int k = 0; k < LC; ++k) {
-                int tx = x0 + k + EX[i];
-                tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
-                dst[tx] = v[k];
+            for (int k = 1; k < LC; ++k) w[k] = v[k - 1];
+            if (left_here) {
+                vstore<LC>(dst + x0, w);
+            } else {
+#pragma unroll
+                for (int k = 1; k < LC; ++k) dst[x0 + k] = w[k];
+            }
+            const bool right_here = lane < 63 && m.c < m.nc - 1;
+            if (!right_here) {
+                const int tx = x0 + LC == nx ? 0 : x0 + LC;
+                dst[tx] = v[LC - 1];
+            }
+        } else {
+            const double from_right = __shfl_down(v[0], 1);
+            const bool right_here = lane < 63 && m.c < m.nc - 1;
+            double w[LC];
+#pragma unroll
+            for (int k = 0; k < LC - 1; ++k) w[k] = v[k + 1];
+            w[LC - 1] = from_right;
+            if (right_here) {
+                vstore<LC>(dst + x0, w);
+            } else {
+#pragma unroll
+                for (int k = 0; k < LC - 1; ++k) dst[x0 + k] = w[k];
+            }
+            const bool left_here = lane > 0 && m.c > 0;
+            if (!left_here) {
+                const int tx = x0 == 0 ? nx - 1 : x0 - 1;
+                dst[tx] = v[0];
             }
         }
     }
@@ -442,12 +480,16 @@ hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const doub
     const int T = row_threads_iir(p);
 #define ARGS                                                                                   \
     dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, mu, fy, fout, o_rho, o_vx, o_vy, o_fx
+    // holding f in registers only pays with 256-thread blocks (no spills)
+    const bool keep = p.row_keep && T <= 256;
     if (observe)
-        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, true>), (k_rows_collide_iir<1024, true>),
-                          ARGS);
+        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, true, false>),
+                          (k_rows_collide_iir<1024, true, false>), ARGS);
+    else if (keep)
+        hipLaunchKernelGGL((k_rows_collide_iir<256, false, true>), ARGS);
     else
-        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, false>), (k_rows_collide_iir<1024, false>),
-                          ARGS);
+        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, false, false>),
+                          (k_rows_collide_iir<1024, false, false>), ARGS);
 #undef ARGS
     return hipGetLastError();
 }

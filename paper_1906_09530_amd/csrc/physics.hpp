@@ -46,24 +46,28 @@ __device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
     const bool outside = (p.eos == 4) ? (b * rho * 0.25 >= 1.0) : (b * rho >= 1.0);
     if (outside) return p.mu_cap;
     double m;
+    const double br = b * rho;
     switch (p.eos) {
-    case 0:  // van der Waals
-        m = RT * (log(rho / (1.0 - b * rho)) + 1.0 / (1.0 - b * rho)) - 2.0 * p.a * rho;
+    case 0: {  // van der Waals
+        const double iv = 1.0 / (1.0 - br);
+        m = RT * (log(rho * iv) + iv) - 2.0 * p.a * rho;
         break;
+    }
     case 1:
-    case 2:  // Redlich-Kwong, Soave-Redlich-Kwong
-        m = RT * log(rho / (1.0 - b * rho)) + RT / (1.0 - b * rho) - A / b * log(1.0 + b * rho) -
-            A * rho / (1.0 + b * rho);
+    case 2: {  // Redlich-Kwong, Soave-Redlich-Kwong; eos_c1 = A / b
+        const double iv = 1.0 / (1.0 - br);
+        m = RT * log(rho * iv) + RT * iv - p.eos_c1 * log(1.0 + br) - A * rho / (1.0 + br);
         break;
-    case 3: {  // Peng-Robinson
+    }
+    case 3: {  // Peng-Robinson; eos_c1 = A / (2 sqrt(2) b)
         const double s2 = 1.4142135623730950488;
-        m = RT * log(rho / (1.0 - b * rho)) -
-            A / (2.0 * s2 * b) * log((s2 - 1.0 + b * rho) / (s2 + 1.0 - b * rho)) +
-            RT / (1.0 - b * rho) - A * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+        const double iv = 1.0 / (1.0 - br);
+        m = RT * log(rho * iv) - p.eos_c1 * log((s2 - 1.0 + br) / (s2 + 1.0 - br)) + RT * iv -
+            A * rho / (1.0 + 2.0 * br - br * br);
         break;
     }
     default: {  // Carnahan-Starling
-        const double eta = b * rho * 0.25, q = 1.0 - eta;
+        const double eta = br * 0.25, q = 1.0 - eta;
         m = RT * ((3.0 - eta) / (q * q * q) + log(rho) + 1.0) - 2.0 * p.a * rho;
         break;
     }

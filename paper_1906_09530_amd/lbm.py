@@ -211,9 +211,9 @@ class Solver:
     def autotune(self, repeats=20):
         """Pick the fastest column-pass shape; returns {(width, chunk): ms}
         (chunk 0: the general reduction kernel)."""
-        w = (C.c_int * 16)()
-        ch = (C.c_int * 16)()
-        ms = (C.c_double * 16)()
+        w = (C.c_int * 24)()
+        ch = (C.c_int * 24)()
+        ms = (C.c_double * 24)()
         n = C.c_int()
         _check(load().lbm_autotune(self.ctx, int(repeats), w, ch, ms, C.byref(n)), self.ctx)
         return {(w[i], ch[i]): ms[i] for i in range(n.value)}
