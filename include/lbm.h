@@ -191,6 +191,67 @@ const char *lbm_last_error(const lbm_ctx *ctx);
 /* Name of a status code. */
 const char *lbm_status_string(lbm_status s);
 
+/* ---- batches of independent simulations --------------------------------
+ * A sweep (temperatures for the coexistence curve of Sec. 5.1, radii for
+ * Laplace's law of Sec. 5.3) runs as one batch: every pass of a time step is
+ * a single launch over the workgroups of all active simulations, a chunk of
+ * steps between convergence tests is replayed from one captured HIP graph,
+ * and simulations that have converged drop out of the launches.  Each
+ * simulation has its own parameters, sizes and state and evolves exactly as
+ * it would in its own context with the same column-pass shape.  The batch
+ * owns its device memory and a HIP stream of its own (default priority). */
+typedef struct lbm_batch lbm_batch;
+
+/* Create a batch of nsims simulations.  params[s], rho0[s], ux0[s], uy0[s]
+ * as for lbm_init (host arrays; ux0/uy0 may be NULL, or hold NULL entries,
+ * for rest).  Each simulation needs 64 <= nx, ny <= 1024 with nx and ny
+ * multiples of 8.  Fails as lbm_init would, naming the simulation in
+ * lbm_batch_last_error(NULL). */
+lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const double *const *rho0,
+                            const double *const *ux0, const double *const *uy0, lbm_batch **out);
+
+/* Set the column-pass shape of the batch: col_elems (2048 or 4096) nodes per
+ * workgroup, i.e. col_elems / ny columns of each simulation, in chunks of
+ * chunk (4 or 8) nodes per thread.  Results do not depend on col_elems. */
+lbm_status lbm_batch_set_column_shape(lbm_batch *b, int col_elems, int chunk);
+
+/* Autotuner: time the batched column pass for each shape above (repeats
+ * launches each, HIP events), keep the fastest.  State unchanged.
+ * col_elems[], chunks[], ms[] (room for 4, may be NULL) and *count report
+ * the candidates. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int repeats, int *col_elems, int *chunks,
+                              double *ms, int *count);
+
+/* Enqueue nsteps steps of every active simulation (eager launches). */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Step all active simulations, test each every check_every steps for
+ * max_x |rho(t) - rho(t - check_every)| < tol, and retire the ones that pass;
+ * stop when none is active or after max_steps steps.  use_graph != 0 replays
+ * each chunk from a captured HIP graph (re-captured when the set of active
+ * simulations changes); 0 launches eagerly.  Per-simulation outputs
+ * (arrays of nsims, each may be NULL): steps taken, last difference, and
+ * status (LBM_OK converged, LBM_NOT_CONVERGED, LBM_E_NONFINITE, which also
+ * retires the simulation).  Returns LBM_OK when all converged,
+ * LBM_E_NONFINITE if any diverged, else LBM_NOT_CONVERGED. */
+lbm_status lbm_batch_run_until_converged(lbm_batch *b, double tol, int64_t check_every,
+                                         int64_t max_steps, int use_graph, int64_t *steps_done,
+                                         double *last_delta, int32_t *status);
+
+/* rho and v = u + F/(2 rho) of simulation sim, host arrays of nx*ny (any may
+ * be NULL); the state f[9][ny][nx] of simulation sim (host).  Synchronise. */
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx, double *vy);
+lbm_status lbm_batch_get_state(lbm_batch *b, int32_t sim, double *f);
+
+/* Steps taken by simulation sim (-1 for an invalid index). */
+int64_t lbm_batch_steps(const lbm_batch *b, int32_t sim);
+
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Reason for the last failure of b, or of the last failed lbm_batch_create
+ * when b is NULL. */
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,9 @@ FLAGS = [
     "--offload-arch=" + ARCH,
     # keep the compiler away from packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a multiply into an add only within one source expression, so that
+    # every kernel instantiating a shared device body rounds identically
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -669,3 +669,488 @@ const char *lbm_status_string(lbm_status s)
 }
 
 }  // extern "C"
+
+// ---- batches of independent simulations -----------------------------------
+
+struct lbm_batch {
+    int n = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<lbm_params> prm;
+    std::vector<KParams> kp;
+    std::vector<SimBuffers> sb;
+    std::vector<size_t> N;
+    std::vector<double *> prev, partial;
+    std::vector<int> red_blocks;
+    KParams *d_kp = nullptr;
+    SimBuffers *d_sb = nullptr;
+    WorkItem *d_rows = nullptr, *d_cols = nullptr;
+    int n_rows = 0, n_cols = 0;
+    double *d_res = nullptr;  // per simulation: max |drho|, non-finite flag
+    void *mem = nullptr;
+    std::vector<int> active;
+    std::vector<int> held;  // parity of the buffer a retired simulation's state is in
+    std::vector<int64_t> steps;
+    std::vector<lbm_status> status;
+    int parity = 0;  // every active simulation holds its state in f[parity]
+    int col_elems = 4096, col_lc = 8;
+    size_t row_lds = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int64_t graph_len = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+lbm_status bfail(lbm_batch *b, lbm_status s, const std::string &msg)
+{
+    if (b)
+        b->err = msg;
+    else
+        g_batch_error = msg;
+    return s;
+}
+
+#define BHIP_OR(b, call)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return bfail((b), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_drop_graphs(lbm_batch *b)
+{
+    for (auto &g : b->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    b->graph_len = 0;
+}
+
+// Column shape of every simulation for the batch's (col_elems, col_lc).
+bool batch_apply_col_shape(lbm_batch *b, int col_elems, int lc)
+{
+    std::vector<KParams> kp = b->kp;
+    for (int s = 0; s < b->n; ++s) {
+        set_col_shape(&kp[s], col_elems / kp[s].ny, lc);
+        if (!kp[s].use_iir_cols || kp[s].cols_per_block * kp[s].ny > col_elems) return false;
+    }
+    b->kp = kp;
+    b->col_elems = col_elems;
+    b->col_lc = lc;
+    return true;
+}
+
+// Upload the parameter blocks and the work tables of the active simulations
+// (largest meshes first, so the longest workgroups start first).
+lbm_status batch_upload(lbm_batch *b)
+{
+    BHIP_OR(b, hipStreamSynchronize(b->stream));
+    BHIP_OR(b, hipMemcpy(b->d_kp, b->kp.data(), sizeof(KParams) * b->n, hipMemcpyHostToDevice));
+    std::vector<int> order;
+    for (int s = 0; s < b->n; ++s)
+        if (b->active[s]) order.push_back(s);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->N[x] > b->N[y]; });
+    std::vector<WorkItem> rows, cols;
+    for (int s : order) {
+        const KParams &k = b->kp[s];
+        for (int y0 = 0; y0 < k.ny; y0 += k.rows_per_block) rows.push_back({s, y0});
+        for (int x0 = 0; x0 < k.nx; x0 += k.cols_per_block) cols.push_back({s, x0});
+    }
+    b->n_rows = (int)rows.size();
+    b->n_cols = (int)cols.size();
+    if (!rows.empty())
+        BHIP_OR(b, hipMemcpy(b->d_rows, rows.data(), sizeof(WorkItem) * rows.size(),
+                             hipMemcpyHostToDevice));
+    if (!cols.empty())
+        BHIP_OR(b, hipMemcpy(b->d_cols, cols.data(), sizeof(WorkItem) * cols.size(),
+                             hipMemcpyHostToDevice));
+    batch_drop_graphs(b);
+    return LBM_OK;
+}
+
+hipError_t batch_enqueue(lbm_batch *b, int64_t nsteps)
+{
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        e = launch_batch_rows_rho(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity, b->row_lds,
+                                  b->stream);
+        if (e == hipSuccess)
+            e = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems,
+                                     b->col_lc, b->stream);
+        if (e == hipSuccess)
+            e = launch_batch_rows_collide(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity,
+                                          b->row_lds, b->stream);
+        b->parity ^= 1;
+    }
+    return e;
+}
+
+// Enqueue nsteps as one graph launch (captured on first use for the
+// current parity and work tables).
+lbm_status batch_enqueue_graph(lbm_batch *b, int64_t nsteps)
+{
+    if (b->graph_len != nsteps) batch_drop_graphs(b);
+    hipGraphExec_t &ex = b->gexec[b->parity];
+    if (!ex) {
+        const int parity0 = b->parity;
+        hipGraph_t g = nullptr;
+        BHIP_OR(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = batch_enqueue(b, nsteps);
+        hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+        b->parity = parity0;
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return bfail(b, LBM_E_DEVICE, std::string("graph capture failed: ") +
+                                              hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return bfail(b, LBM_E_DEVICE,
+                         std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        b->graph_len = nsteps;
+    }
+    BHIP_OR(b, hipGraphLaunch(ex, b->stream));
+    if (nsteps & 1) b->parity ^= 1;
+    return LBM_OK;
+}
+
+int sim_parity(const lbm_batch *b, int s) { return b->active[s] ? b->parity : b->held[s]; }
+
+lbm_status benter(lbm_batch *b)
+{
+    if (!b) return LBM_E_INVALID;
+    BHIP_OR(b, hipSetDevice(b->device));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const double *const *rho0,
+                            const double *const *ux0, const double *const *uy0, lbm_batch **out)
+{
+    if (!out) return bfail(nullptr, LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    g_batch_error.clear();
+    if (nsims <= 0 || !params || !rho0) return bfail(nullptr, LBM_E_INVALID, "no simulations");
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    auto give_up = [&](lbm_status st, const std::string &m) {
+        std::string msg = m;
+        lbm_batch_destroy(b);
+        return bfail(nullptr, st, msg);
+    };
+    b->n = nsims;
+    b->prm.assign(params, params + nsims);
+    b->kp.resize(nsims);
+    for (int s = 0; s < nsims; ++s) {
+        const lbm_params *p = &params[s];
+        const std::string who = "simulation " + std::to_string(s) + ": ";
+        std::string why;
+        lbm_status st = validate(p, &why);
+        if (st != LBM_OK) return give_up(st, who + why);
+        if (p->nx < 64 || p->ny < 64 || p->nx > 1024 || p->ny > 1024 || p->nx % 8 || p->ny % 8)
+            return give_up(LBM_E_INVALID, who + "batch meshes need 64 <= nx, ny <= 1024, multiples of 8");
+        if (!make_kparams(p, &b->kp[s], &why)) return give_up(LBM_E_INVALID, who + why);
+        if (!b->kp[s].use_iir_rows) return give_up(LBM_E_INVALID, who + "row pass shape");
+        if (!rho0[s]) return give_up(LBM_E_INVALID, who + "rho0 is NULL");
+        st = check_density(p, rho0[s], ux0 ? ux0[s] : nullptr, uy0 ? uy0[s] : nullptr,
+                           (size_t)p->nx * p->ny, &why);
+        if (st != LBM_OK) return give_up(st, who + why);
+    }
+    if (!batch_apply_col_shape(b, 4096, 8)) return give_up(LBM_E_INVALID, "column shape");
+    if (hipGetDevice(&b->device) != hipSuccess) return give_up(LBM_E_DEVICE, "no HIP device");
+    if (hipStreamCreate(&b->stream) != hipSuccess) return give_up(LBM_E_DEVICE, "hipStreamCreate");
+
+    // one allocation: per simulation f A/B, rho, dxx, mu, fy, prev, partials
+    size_t total = 0;
+    std::vector<size_t> off(nsims);
+    b->N.resize(nsims);
+    b->red_blocks.resize(nsims);
+    for (int s = 0; s < nsims; ++s) {
+        const size_t N = (size_t)params[s].nx * params[s].ny;
+        b->N[s] = N;
+        b->red_blocks[s] = rho_delta_blocks(b->kp[s]);
+        off[s] = total;
+        total += 2 * align256(9 * N * sizeof(double)) + 5 * align256(N * sizeof(double)) +
+                 align256(2 * (size_t)b->red_blocks[s] * sizeof(double));
+    }
+    if (hipMalloc(&b->mem, total) != hipSuccess) return give_up(LBM_E_NOMEM, "hipMalloc failed");
+    size_t rows_cap = 0, cols_cap = 0;
+    b->sb.resize(nsims);
+    b->prev.resize(nsims);
+    b->partial.resize(nsims);
+    for (int s = 0; s < nsims; ++s) {
+        char *m = (char *)b->mem + off[s];
+        const size_t N = b->N[s];
+        SimBuffers &q = b->sb[s];
+        q.f[0] = (double *)m;
+        m += align256(9 * N * sizeof(double));
+        q.f[1] = (double *)m;
+        m += align256(9 * N * sizeof(double));
+        double **planes[] = {&q.rho, &q.dxx, &q.mu, &q.fy, &b->prev[s]};
+        for (double **pl : planes) {
+            *pl = (double *)m;
+            m += align256(N * sizeof(double));
+        }
+        b->partial[s] = (double *)m;
+        rows_cap += (params[s].ny + b->kp[s].rows_per_block - 1) / b->kp[s].rows_per_block;
+        cols_cap += params[s].nx;  // at most one column per workgroup
+        const size_t re = (size_t)b->kp[s].rows_per_block * params[s].nx;
+        b->row_lds = std::max(b->row_lds, batch_row_lds((int)re));
+    }
+    if (hipMalloc(&b->d_kp, sizeof(KParams) * nsims) != hipSuccess ||
+        hipMalloc(&b->d_sb, sizeof(SimBuffers) * nsims) != hipSuccess ||
+        hipMalloc(&b->d_rows, sizeof(WorkItem) * rows_cap) != hipSuccess ||
+        hipMalloc(&b->d_cols, sizeof(WorkItem) * cols_cap) != hipSuccess ||
+        hipMalloc(&b->d_res, sizeof(double) * 2 * nsims) != hipSuccess)
+        return give_up(LBM_E_NOMEM, "hipMalloc failed");
+    if (hipMemcpy(b->d_sb, b->sb.data(), sizeof(SimBuffers) * nsims, hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return give_up(LBM_E_DEVICE, "upload of buffers failed");
+    // initial state f = feq(rho0, u0); the fields planes stage the inputs
+    for (int s = 0; s < nsims; ++s) {
+        const size_t N = b->N[s];
+        const SimBuffers &q = b->sb[s];
+        hipError_t e = hipMemcpy(q.rho, rho0[s], N * sizeof(double), hipMemcpyHostToDevice);
+        const double *dux = nullptr, *duy = nullptr;
+        if (e == hipSuccess && ux0 && ux0[s]) {
+            e = hipMemcpy(q.dxx, ux0[s], N * sizeof(double), hipMemcpyHostToDevice);
+            dux = q.dxx;
+        }
+        if (e == hipSuccess && uy0 && uy0[s]) {
+            e = hipMemcpy(q.mu, uy0[s], N * sizeof(double), hipMemcpyHostToDevice);
+            duy = q.mu;
+        }
+        if (e == hipSuccess) e = launch_init_feq(b->kp[s], q.rho, dux, duy, q.f[0], b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess)
+            return give_up(LBM_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
+    }
+    b->active.assign(nsims, 1);
+    b->held.assign(nsims, 0);
+    b->steps.assign(nsims, 0);
+    b->status.assign(nsims, LBM_NOT_CONVERGED);
+    lbm_status st = batch_upload(b);
+    if (st != LBM_OK) return give_up(st, b->err);
+    *out = b;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_column_shape(lbm_batch *b, int col_elems, int chunk)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if ((col_elems != 2048 && col_elems != 4096) || (chunk != 4 && chunk != 8))
+        return bfail(b, LBM_E_INVALID, "col_elems must be 2048 or 4096 and chunk 4 or 8");
+    if (!batch_apply_col_shape(b, col_elems, chunk))
+        return bfail(b, LBM_E_INVALID, "shape does not fit every simulation");
+    return batch_upload(b);
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int repeats, int *col_elems, int *chunks, double *ms,
+                              int *count)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (repeats <= 0) return bfail(b, LBM_E_INVALID, "repeats must be positive");
+    // the column pass writes mu and F_y only: the state is untouched
+    BHIP_OR(b, launch_batch_rows_rho(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity,
+                                     b->row_lds, b->stream));
+    hipEvent_t e0, e1;
+    BHIP_OR(b, hipEventCreate(&e0));
+    BHIP_OR(b, hipEventCreate(&e1));
+    const int cand[4][2] = {{2048, 4}, {4096, 4}, {2048, 8}, {4096, 8}};
+    int n = 0, best = -1;
+    double best_ms = INFINITY;
+    hipError_t err = hipSuccess;
+    for (int c = 0; c < 4 && err == hipSuccess; ++c) {
+        if (!batch_apply_col_shape(b, cand[c][0], cand[c][1])) continue;
+        if (batch_upload(b) != LBM_OK) break;
+        err = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems, b->col_lc,
+                                   b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+        for (int r = 0; r < repeats && err == hipSuccess; ++r)
+            err = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems,
+                                       b->col_lc, b->stream);
+        if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        if (err != hipSuccess) break;
+        if (col_elems) col_elems[n] = cand[c][0];
+        if (chunks) chunks[n] = cand[c][1];
+        if (ms) ms[n] = t / repeats;
+        ++n;
+        if (t < best_ms) {
+            best_ms = t;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return bfail(b, LBM_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(err));
+    if (best < 0 || !batch_apply_col_shape(b, cand[best][0], cand[best][1]))
+        return bfail(b, LBM_E_INVALID, "no column shape fits");
+    if (count) *count = n;
+    return batch_upload(b);
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (nsteps < 0) return bfail(b, LBM_E_INVALID, "nsteps must be >= 0");
+    BHIP_OR(b, batch_enqueue(b, nsteps));
+    for (int s = 0; s < b->n; ++s)
+        if (b->active[s]) b->steps[s] += nsteps;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_run_until_converged(lbm_batch *b, double tol, int64_t check_every,
+                                         int64_t max_steps, int use_graph, int64_t *steps_done,
+                                         double *last_delta, int32_t *status)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (check_every <= 0 || max_steps < 0 || !(tol >= 0))
+        return bfail(b, LBM_E_INVALID, "check_every > 0, max_steps >= 0, tol >= 0 required");
+    const int n = b->n;
+    std::vector<double> res(2 * n), delta(n, INFINITY);
+    std::vector<int64_t> taken(n, 0);
+    // rho of each active simulation against its value at the previous test;
+    // record: keep the differences and retire non-finite simulations, and
+    // (may_converge) those below tol
+    auto check_all = [&](bool record, bool may_converge) -> lbm_status {
+        for (int s = 0; s < n; ++s)
+            if (b->active[s])
+                BHIP_OR(b, launch_rho_delta(b->kp[s], b->sb[s].f[b->parity], b->prev[s],
+                                            b->partial[s], b->red_blocks[s], b->d_res + 2 * s,
+                                            b->stream));
+        BHIP_OR(b, hipMemcpyAsync(res.data(), b->d_res, sizeof(double) * 2 * n,
+                                  hipMemcpyDeviceToHost, b->stream));
+        BHIP_OR(b, hipStreamSynchronize(b->stream));
+        if (!record) return LBM_OK;
+        bool changed = false;
+        for (int s = 0; s < n; ++s) {
+            if (!b->active[s]) continue;
+            delta[s] = res[2 * s];
+            if (res[2 * s + 1] != 0.0) {
+                b->status[s] = LBM_E_NONFINITE;
+                delta[s] = NAN;
+            } else if (may_converge && delta[s] < tol) {
+                b->status[s] = LBM_OK;
+            } else {
+                continue;
+            }
+            b->held[s] = b->parity;
+            b->active[s] = 0;
+            changed = true;
+        }
+        return changed ? batch_upload(b) : LBM_OK;
+    };
+    if ((st = check_all(false, false)) != LBM_OK) return st;
+    int64_t done = 0;
+    bool any = true;
+    while (done < max_steps && any) {
+        int64_t chunk = check_every;
+        if (done + chunk > max_steps) chunk = max_steps - done;
+        if (use_graph && chunk == check_every)
+            st = batch_enqueue_graph(b, chunk);
+        else
+            st = batch_enqueue(b, chunk) == hipSuccess ? LBM_OK
+                                                        : bfail(b, LBM_E_DEVICE, "launch failed");
+        if (st != LBM_OK) return st;
+        for (int s = 0; s < n; ++s)
+            if (b->active[s]) {
+                b->steps[s] += chunk;
+                taken[s] += chunk;
+            }
+        done += chunk;
+        // a shorter last chunk is not a whole test interval: it cannot converge
+        if ((st = check_all(true, chunk == check_every)) != LBM_OK) return st;
+        any = false;
+        for (int s = 0; s < n; ++s) any = any || b->active[s];
+    }
+    bool all_ok = true, bad = false;
+    for (int s = 0; s < n; ++s) {
+        if (steps_done) steps_done[s] = taken[s];
+        if (last_delta) last_delta[s] = delta[s];
+        if (status) status[s] = b->status[s];
+        all_ok = all_ok && b->status[s] == LBM_OK;
+        bad = bad || b->status[s] == LBM_E_NONFINITE;
+    }
+    return bad ? LBM_E_NONFINITE : (all_ok ? LBM_OK : LBM_NOT_CONVERGED);
+}
+
+lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx, double *vy)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (sim < 0 || sim >= b->n) return bfail(b, LBM_E_INVALID, "no such simulation");
+    const KParams &k = b->kp[sim];
+    const SimBuffers &q = b->sb[sim];
+    const size_t N = b->N[sim];
+    double *obs = nullptr;
+    BHIP_OR(b, hipMalloc(&obs, 3 * N * sizeof(double)));
+    const double *fc = q.f[sim_parity(b, sim)];
+    hipError_t e = launch_rows_rho(k, fc, q.rho, q.dxx, b->stream);
+    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.dxx, q.mu, q.fy, b->stream);
+    if (e == hipSuccess)
+        e = launch_rows_observe(k, fc, q.mu, q.fy, obs, obs + N, obs + 2 * N, nullptr, b->stream);
+    double *outs[3] = {rho, vx, vy};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        if (outs[i])
+            e = hipMemcpyAsync(outs[i], obs + i * N, N * sizeof(double), hipMemcpyDeviceToHost,
+                               b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(obs);
+    if (e != hipSuccess)
+        return bfail(b, LBM_E_DEVICE, std::string("moments: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_state(lbm_batch *b, int32_t sim, double *f)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (sim < 0 || sim >= b->n || !f) return bfail(b, LBM_E_INVALID, "no such simulation");
+    BHIP_OR(b, hipMemcpyAsync(f, b->sb[sim].f[sim_parity(b, sim)], 9 * b->N[sim] * sizeof(double),
+                              hipMemcpyDeviceToHost, b->stream));
+    BHIP_OR(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+int64_t lbm_batch_steps(const lbm_batch *b, int32_t sim)
+{
+    if (!b || sim < 0 || sim >= b->n) return -1;
+    return b->steps[sim];
+}
+
+void lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    void *ptrs[] = {b->mem, b->d_kp, b->d_sb, b->d_rows, b->d_cols, b->d_res};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b)
+{
+    return b ? b->err.c_str() : g_batch_error.c_str();
+}
+
+}  // extern "C"

@@ -71,6 +71,31 @@ int rho_delta_blocks(const KParams &p);
 void set_row_shape(KParams *p);
 void set_col_shape(KParams *p, int width, int chunk);
 
+// ---- batches of independent meshes ------------------------------------
+// Device-side buffers of one mesh of a batch.
+struct SimBuffers {
+    double *f[2];
+    double *rho, *dxx, *mu, *fy;
+};
+// One workgroup of a batched pass: the mesh and its first row or column.
+struct WorkItem {
+    int sim, start;
+};
+// LDS of a batched row block holding rows_elems nodes, and of a batched
+// column block of col_elems nodes in chunks of lc.
+size_t batch_row_lds(int rows_elems);
+size_t batch_col_lds(int col_elems, int lc);
+// Batched passes: rows use 256-thread workgroups (each mesh's rows_per_block
+// rows of nx <= 1024 nodes); the column pass uses col_elems / lc threads
+// (each mesh's cols_per_block = col_elems / ny columns), lc = 4 or 8.
+hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
+                                 int nwork, int parity, size_t lds, hipStream_t s);
+hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
+                                int nwork, int col_elems, int lc, hipStream_t s);
+hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
+                                     const WorkItem *work, int nwork, int parity, size_t lds,
+                                     hipStream_t s);
+
 // Fast-path kernels (kernels_iir.hip) and their eligibility.
 bool iir_rows_ok(const KParams &p);
 bool iir_cols_ok(const KParams &p, int chunk, int width);

@@ -158,16 +158,15 @@ __device__ __forceinline__ Chunk<LC> row_chunk(const KParams &p, int rows)
 
 constexpr int kRowLC = 4;
 
-template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ f,
-                                                       double *__restrict__ rho_out,
-                                                       double *__restrict__ dxx_out)
+// Pass A on rows [y0, y0 + rows_per_block) of one mesh.
+__device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const double *__restrict__ f,
+                                              double *__restrict__ rho_out,
+                                              double *__restrict__ dxx_out)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
-    const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
     double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
@@ -194,7 +193,14 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *
     if (m.ok) vstore<LC>(dxx_out + base, d2);
 }
 
-template <int LC>
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ f,
+                                                       double *__restrict__ rho_out,
+                                                       double *__restrict__ dxx_out)
+{
+    rows_rho_body(p, blockIdx.x * p.rows_per_block, f, rho_out, dxx_out);
+}
+
 __device__ __forceinline__ int strip_of_block(const KParams &p)
 {
     const int b = blockIdx.x, g = p.col_xcd_groups;
@@ -203,15 +209,18 @@ __device__ __forceinline__ int strip_of_block(const KParams &p)
     return (b % g) * per + b / g;
 }
 
-template <int LC, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *__restrict__ rho,
-                                                      const double *__restrict__ dxx,
-                                                      double *__restrict__ mu_out,
-                                                      double *__restrict__ fy_out)
+// Pass B on columns [x0, x0 + cols_per_block) of one mesh.  Threads beyond
+// the strip's chunks (a batch launch sized for the largest strip) only take
+// part in the barriers.
+template <int LC>
+__device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
+                                             const double *__restrict__ rho,
+                                             const double *__restrict__ dxx,
+                                             double *__restrict__ mu_out,
+                                             double *__restrict__ fy_out)
 {
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny, W = p.cols_per_block;
-    const int x0 = strip_of_block<LC>(p) * W;
     const int cols = min(W, nx - x0);
     Chunk<LC> m;
     m.n = ny;
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
     m.mirror = p.bc_y != 0;
     m.c = threadIdx.x / W;
     m.l = threadIdx.x - m.c * W;
-    m.ok = m.l < cols;
+    m.ok = m.l < cols && m.c < m.nc;
     double *vbuf = smem, *cP = smem + W * ny, *cB = cP + W * m.nc;
     const size_t col = x0 + m.l;
     const int j0 = m.c * LC;
@@ -251,12 +260,22 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
     }
 }
 
+template <int LC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *__restrict__ rho,
+                                                      const double *__restrict__ dxx,
+                                                      double *__restrict__ mu_out,
+                                                      double *__restrict__ fy_out)
+{
+    cols_mu_body<LC>(p, strip_of_block(p) * p.cols_per_block, rho, dxx, mu_out, fy_out);
+}
+
+// Pass C on rows [y0, y0 + rows_per_block) of one mesh.
 // KEEP: the nine populations stay in registers from the first read to the
 // collision; otherwise each is read again when needed (fewer registers, so
 // more waves per SIMD; the second read is served by the caches).
-template <int MAXT, bool OBSERVE, bool KEEP>
-__global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
-    KParams p, const double *__restrict__ f, const double *__restrict__ mu,
+template <bool OBSERVE, bool KEEP>
+__device__ __forceinline__ void rows_collide_body(
+    const KParams &p, int y0, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
     double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
 {
@@ -264,7 +283,6 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
-    const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
     double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
@@ -412,7 +430,96 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     }
 }
 
+template <int MAXT, bool OBSERVE, bool KEEP>
+__global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
+    KParams p, const double *__restrict__ f, const double *__restrict__ mu,
+    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
+    double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
+{
+    rows_collide_body<OBSERVE, KEEP>(p, blockIdx.x * p.rows_per_block, f, mu, fy, fout, o_rho,
+                                     o_vx, o_vy, o_fx);
+}
+
+// ---- batched passes: one launch covers the blocks of every active mesh ----
+// Work item b names the mesh and its first row (row passes) or column
+// (column pass); each mesh has its own parameter block and buffers.  parity
+// selects which of the mesh's two distribution buffers holds the state.
+
+__global__ __launch_bounds__(256) void kb_rows_rho(const KParams *__restrict__ kps,
+                                                   const SimBuffers *__restrict__ sb,
+                                                   const WorkItem *__restrict__ work, int parity)
+{
+    const WorkItem w = work[blockIdx.x];
+    const SimBuffers &b = sb[w.sim];
+    rows_rho_body(kps[w.sim], w.start, b.f[parity], b.rho, b.dxx);
+}
+
+template <int LC, int MAXT>
+__global__ __launch_bounds__(MAXT) void kb_cols_mu(const KParams *__restrict__ kps,
+                                                   const SimBuffers *__restrict__ sb,
+                                                   const WorkItem *__restrict__ work)
+{
+    const WorkItem w = work[blockIdx.x];
+    const SimBuffers &b = sb[w.sim];
+    cols_mu_body<LC>(kps[w.sim], w.start, b.rho, b.dxx, b.mu, b.fy);
+}
+
+__global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict__ kps,
+                                                       const SimBuffers *__restrict__ sb,
+                                                       const WorkItem *__restrict__ work,
+                                                       int parity)
+{
+    const WorkItem w = work[blockIdx.x];
+    const SimBuffers &b = sb[w.sim];
+    rows_collide_body<false, true>(kps[w.sim], w.start, b.f[parity], b.mu, b.fy,
+                                   b.f[1 - parity], nullptr, nullptr, nullptr, nullptr);
+}
+
 }  // namespace
+
+size_t batch_row_lds(int rows_elems)
+{
+    return sizeof(double) * ((size_t)rows_elems + 2 * (size_t)rows_elems / kRowLC);
+}
+
+size_t batch_col_lds(int col_elems, int lc)
+{
+    return sizeof(double) * ((size_t)col_elems + 2 * (size_t)col_elems / lc);
+}
+
+hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
+                                 int nwork, int parity, size_t lds, hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_rows_rho, dim3(nwork), dim3(256), lds, s, kps, sb, work, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
+                                int nwork, int col_elems, int lc, hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    const int T = col_elems / lc;
+    const size_t lds = batch_col_lds(col_elems, lc);
+    if (lc == 4 && T <= 256)
+        hipLaunchKernelGGL((kb_cols_mu<4, 256>), dim3(nwork), dim3(T), lds, s, kps, sb, work);
+    else if (lc == 4)
+        hipLaunchKernelGGL((kb_cols_mu<4, 1024>), dim3(nwork), dim3(T), lds, s, kps, sb, work);
+    else if (T <= 256)
+        hipLaunchKernelGGL((kb_cols_mu<8, 256>), dim3(nwork), dim3(T), lds, s, kps, sb, work);
+    else
+        hipLaunchKernelGGL((kb_cols_mu<8, 1024>), dim3(nwork), dim3(T), lds, s, kps, sb, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
+                                     const WorkItem *work, int nwork, int parity, size_t lds,
+                                     hipStream_t s)
+{
+    if (nwork <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_rows_collide, dim3(nwork), dim3(256), lds, s, kps, sb, work, parity);
+    return hipGetLastError();
+}
 
 bool iir_rows_ok(const KParams &p)
 {

@@ -85,6 +85,19 @@ def load():
         "lbm_destroy": (None, [P]),
         "lbm_last_error": (C.c_char_p, [P]),
         "lbm_status_string": (C.c_char_p, [i32]),
+        "lbm_batch_create": (i32, [i32, pp, C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                                   C.POINTER(P)]),
+        "lbm_batch_set_column_shape": (i32, [P, i32, i32]),
+        "lbm_batch_autotune": (i32, [P, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), pd,
+                                     C.POINTER(C.c_int)]),
+        "lbm_batch_step": (i32, [P, i64]),
+        "lbm_batch_run_until_converged": (i32, [P, d, i64, i64, i32, C.POINTER(i64), pd,
+                                                C.POINTER(C.c_int32)]),
+        "lbm_batch_moments": (i32, [P, i32, P, P, P]),
+        "lbm_batch_get_state": (i32, [P, i32, P]),
+        "lbm_batch_steps": (i64, [P, i32]),
+        "lbm_batch_destroy": (None, [P]),
+        "lbm_batch_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -235,3 +248,88 @@ class Solver:
         if not dev:
             f = np.ascontiguousarray(f, dtype=np.float64)
         _check(load().lbm_set_state(self.ctx, _ptr(f), int(dev)), self.ctx)
+
+
+def _bcheck(st, b=None, ok=(LBM_OK,)):
+    if st not in ok:
+        raise LBMError(st, load().lbm_batch_last_error(b).decode())
+    return st
+
+
+class Batch:
+    """Independent simulations stepped together (an lbm_batch): one launch per
+    pass covers every active simulation; converged ones drop out."""
+
+    def __init__(self, plist, rho0s, ux0s=None, uy0s=None):
+        lib = load()
+        n = len(plist)
+        if len(rho0s) != n:
+            raise ValueError("one initial density per simulation")
+        self.plist = list(plist)
+        self.n = n
+        arr = (Params * n)(*plist)
+
+        def host(a):
+            return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+        rho0s = [host(a) for a in rho0s]
+        ux0s = [None] * n if ux0s is None else [host(a) for a in ux0s]
+        uy0s = [None] * n if uy0s is None else [host(a) for a in uy0s]
+        self._keep = (arr, rho0s, ux0s, uy0s)
+
+        def ptrs(lst):
+            return (C.c_void_p * n)(*[None if a is None else a.ctypes.data for a in lst])
+
+        b = C.c_void_p()
+        st = lib.lbm_batch_create(n, arr, ptrs(rho0s), ptrs(ux0s), ptrs(uy0s), C.byref(b))
+        _bcheck(st, None)
+        self.b = b
+
+    def close(self):
+        if getattr(self, "b", None):
+            load().lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_column_shape(self, col_elems, chunk):
+        _bcheck(load().lbm_batch_set_column_shape(self.b, int(col_elems), int(chunk)), self.b)
+
+    def autotune(self, repeats=20):
+        """Pick the fastest batched column-pass shape; {(col_elems, chunk): ms}."""
+        ce, ch, ms, k = (C.c_int * 4)(), (C.c_int * 4)(), (C.c_double * 4)(), C.c_int()
+        _bcheck(load().lbm_batch_autotune(self.b, int(repeats), ce, ch, ms, C.byref(k)), self.b)
+        return {(ce[i], ch[i]): ms[i] for i in range(k.value)}
+
+    def step(self, n=1):
+        _bcheck(load().lbm_batch_step(self.b, int(n)), self.b)
+
+    def run_until_converged(self, tol, check_every=100, max_steps=10 ** 7, use_graph=True):
+        """Returns (status, steps[], delta[], per-simulation status[])."""
+        steps = (C.c_int64 * self.n)()
+        delta = (C.c_double * self.n)()
+        sts = (C.c_int32 * self.n)()
+        st = load().lbm_batch_run_until_converged(self.b, tol, int(check_every), int(max_steps),
+                                                  int(bool(use_graph)), steps, delta, sts)
+        _bcheck(st, self.b, ok=(LBM_OK, LBM_NOT_CONVERGED, LBM_E_NONFINITE))
+        return st, list(steps), list(delta), list(sts)
+
+    def steps_taken(self, sim):
+        return load().lbm_batch_steps(self.b, int(sim))
+
+    def moments(self, sim):
+        p = self.plist[sim]
+        r, vx, vy = (np.empty((p.ny, p.nx)) for _ in range(3))
+        _bcheck(load().lbm_batch_moments(self.b, int(sim), r.ctypes.data, vx.ctypes.data,
+                                         vy.ctypes.data), self.b)
+        return r, vx, vy
+
+    def get_state(self, sim):
+        p = self.plist[sim]
+        f = np.empty((9, p.ny, p.nx))
+        _bcheck(load().lbm_batch_get_state(self.b, int(sim), f.ctypes.data), self.b)
+        return f

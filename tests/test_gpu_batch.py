@@ -1,0 +1,194 @@
+"""Batched sweeps (lbm_batch_*): many independent simulations stepped by one
+launch per pass, with per-simulation convergence tests and retirement.
+
+Every simulation of a batch must evolve exactly as it does in its own
+context with the same column-pass chunk length (bitwise), the captured-graph
+and eager loops must agree bitwise on every replay, and the batch must match
+the oracle to the single-simulation bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import analytic as A
+from paper_1906_09530_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _slab(T_r, nx, ny, k):
+    p = lbm.params(lbm.EOS_CS, T_r, nx, ny, kappa=0.1, tau=1.0, k=k)
+    g, l = lbm.maxwell(p)
+    return p, inputs.slab(nx, ny, g, l, 4.0)
+
+
+def _pr_drop(nx, ny, seed):
+    p = lbm.params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0)
+    g, l = lbm.maxwell(p)
+    return p, inputs.droplet(nx, ny, g, l, min(nx, ny) / 4.0, 5.0, seed=seed, noise=1e-6)
+
+
+def _splash(nx, ny, frame):
+    p = lbm.params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0, bc_y=1,
+                   wall_ux=frame)
+    g, l = lbm.maxwell(p)
+    return p, inputs.splash(nx, ny, g, l, radius=16.0, width=5.0, film=12, drop_uy=-0.05,
+                            frame_ux=frame)
+
+
+def _mixed_cases():
+    return [_slab(0.8, 64, 64, 0.3), _pr_drop(128, 96, 3), _splash(160, 96, 0.02),
+            _slab(0.75, 64, 96, 0.25)]
+
+
+def _batch(cases):
+    ps = [c[0] for c in cases]
+    return lbm.Batch(ps, [c[1][0] for c in cases], [c[1][1] for c in cases],
+                     [c[1][2] for c in cases])
+
+
+def _solver(case, col_elems=4096, chunk=8):
+    p, (rho0, ux0, uy0) = case
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    s.set_column_shape(col_elems // p.ny, chunk)
+    return s
+
+
+def test_batch_matches_individual_runs_bitwise():
+    cases = _mixed_cases()
+    print("\n[case] batch of %d: %s" % (len(cases), [(c[0].nx, c[0].ny) for c in cases]),
+          flush=True)
+    b = _batch(cases)
+    solos = [_solver(c) for c in cases]
+    for n in (1, 199, 300):
+        b.step(n)
+        for i, s in enumerate(solos):
+            s.step(n)
+            np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)
+    for i, s in enumerate(solos):
+        for got, want in zip(b.moments(i), s.moments()):
+            np.testing.assert_array_equal(got, want)
+        assert b.steps_taken(i) == 500
+
+
+def test_batch_matches_oracle():
+    """A PR drop (periodic) and a CS splash between sliding walls, 1000 steps
+    as one batch, against the oracle at the single-simulation bar."""
+    cases = [_pr_drop(64, 64, 5), _splash(72, 64, 0.02)]
+    b = _batch(cases)
+    b.step(1000)
+    for i, (p, (rho0, ux0, uy0)) in enumerate(cases):
+        op = A.params(p.eos, p.T_r, p.nx, p.ny, kappa=p.kappa, tau=p.tau, k=p.k,
+                      mu_cap=p.mu_cap, bc_y=p.bc_y, wall_ux=p.wall_ux)
+        f = oracle.init(op, rho0, ux0, uy0)
+        oracle.run(op, f, 1000)
+        r2, vx2, vy2 = oracle.moments(op, f)
+        r, vx, vy = b.moments(i)
+        er = np.max(np.abs(r - r2) / np.abs(r2))
+        vmax = max(np.abs(vx2).max(), np.abs(vy2).max())
+        ev = max(np.abs(vx - vx2).max(), np.abs(vy - vy2).max()) / vmax
+        print("sim %d: rel err rho %.2e, v %.2e" % (i, er, ev), flush=True)
+        assert er <= TOL and ev <= TOL
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_run_until_converged_retires_like_individual_runs(use_graph):
+    """Slabs converging at different times (about 7800 and 18500 steps at
+    tol 1e-10), one that does not within the step budget, and a drop: each
+    simulation's steps, last difference, status and final state equal those
+    of its own context's convergence loop; retired simulations stay frozen
+    while the others go on."""
+    cases = [_slab(0.8, 64, 64, 0.3), _slab(0.75, 64, 96, 0.25), _slab(0.7, 64, 128, 0.2),
+             _pr_drop(96, 96, 8)]
+    tol, every, budget = 1e-10, 100, 20000
+    b = _batch(cases)
+    st, steps, delta, sts = b.run_until_converged(tol, every, budget, use_graph=use_graph)
+    print("\nbatch: status %d, steps %s, delta %s, per-sim %s" % (st, steps, delta, sts),
+          flush=True)
+    assert st == lbm.LBM_NOT_CONVERGED
+    assert sts[0] == lbm.LBM_OK and sts[1] == lbm.LBM_OK
+    assert steps[0] < steps[1] < budget
+    for i, c in enumerate(cases):
+        s = _solver(c)
+        st1, n1, d1 = s.run_until_converged(tol, every, budget)
+        assert sts[i] == st1, i
+        assert steps[i] == n1 and b.steps_taken(i) == n1, i
+        assert delta[i] == d1, i
+        np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)
+
+
+def test_graph_replays_match_eager_on_every_replay():
+    """The captured chunk is replayed many times, with the loop's own eager
+    work (difference kernels, copies, synchronisation) in between; after each
+    call the state equals the eager batch's bitwise."""
+    cases = _mixed_cases()
+    g = _batch(cases)
+    e = _batch(cases)
+    for call in range(4):
+        # tol 0: nothing retires, every chunk is a graph replay
+        rg = g.run_until_converged(0.0, 50, 250, use_graph=True)
+        re = e.run_until_converged(0.0, 50, 250, use_graph=False)
+        assert rg == re
+        for i in range(len(cases)):
+            np.testing.assert_array_equal(g.get_state(i), e.get_state(i),
+                                          err_msg="call %d sim %d" % (call, i))
+    # a shorter chunk length (a new graph) and an odd one (parity flips)
+    for every in (7, 7, 25):
+        assert (g.run_until_converged(0.0, every, 3 * every, use_graph=True) ==
+                e.run_until_converged(0.0, every, 3 * every, use_graph=False))
+        for i in range(len(cases)):
+            np.testing.assert_array_equal(g.get_state(i), e.get_state(i))
+
+
+def test_nonfinite_simulation_is_retired_alone():
+    """An unstable PR drop (k = 0.5, kappa = 0.1) diverges inside a batch:
+    it is reported and retired, and the stable slab beside it converges as on
+    its own."""
+    n = 64
+    p = lbm.params(lbm.EOS_PR, 0.5, n, n, kappa=0.1, tau=0.8, k=0.5, mu_cap=6.0)
+    g, l = lbm.maxwell(p)
+    bad = (p, inputs.droplet(n, n, g, l, 20.0, 10.0))
+    good = _slab(0.8, 64, 64, 0.3)
+    b = _batch([bad, good])
+    st, steps, delta, sts = b.run_until_converged(1e-10, 100, 20000)
+    assert st == lbm.LBM_E_NONFINITE
+    assert sts == [lbm.LBM_E_NONFINITE, lbm.LBM_OK]
+    assert np.isnan(delta[0])
+    s = _solver(good)
+    _, n1, d1 = s.run_until_converged(1e-10, 100, 20000)
+    assert steps[1] == n1 and delta[1] == d1
+    np.testing.assert_array_equal(b.get_state(1), s.get_state())
+
+
+def test_autotune_keeps_state_and_results():
+    cases = _mixed_cases()
+    b = _batch(cases)
+    b.step(10)
+    before = [b.get_state(i) for i in range(len(cases))]
+    table = b.autotune(3)
+    print("\nbatch column shapes (ms): %s" % table, flush=True)
+    assert len(table) == 4 and all(v > 0 for v in table.values())
+    for i in range(len(cases)):
+        np.testing.assert_array_equal(b.get_state(i), before[i])
+    ce, ch = min(table, key=table.get)
+    b.step(90)
+    for i, c in enumerate(cases):
+        s = _solver(c)  # the batch's shape before tuning
+        s.step(10)
+        s.set_column_shape(ce // c[0].ny, ch)
+        s.step(90)
+        np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)
+
+
+@pytest.mark.parametrize("col_elems,chunk", [(2048, 4), (2048, 8), (4096, 4)])
+def test_every_batch_column_shape_matches_individual_runs(col_elems, chunk):
+    cases = _mixed_cases()
+    b = _batch(cases)
+    b.set_column_shape(col_elems, chunk)
+    b.step(40)
+    for i, c in enumerate(cases):
+        s = _solver(c, col_elems, chunk)
+        s.step(40)
+        np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)

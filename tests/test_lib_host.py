@@ -99,3 +99,35 @@ def test_init_domain_check_depends_on_the_upper_limit():
     assert st == lbm.LBM_E_DOMAIN and "domain" in msg
     p.mu_cap = 6.0
     assert lbm.workspace_bytes(p) > 9 * 2 * 16 * 16 * 8
+
+
+def _batch_status(plist, rhos):
+    n = len(plist)
+    arr = (lbm.Params * n)(*plist)
+    rhos = [np.ascontiguousarray(r, dtype=np.float64) for r in rhos]
+    ptrs = (C.c_void_p * n)(*[r.ctypes.data for r in rhos])
+    b = C.c_void_p()
+    st = lbm.load().lbm_batch_create(n, arr, ptrs, None, None, C.byref(b))
+    assert b.value is None
+    return st, lbm.load().lbm_batch_last_error(None).decode()
+
+
+@pytest.mark.parametrize("nx,ny", [(60, 64), (64, 60), (56, 64), (1032, 64), (64, 2048)])
+def test_batch_rejects_sizes_outside_its_range(nx, ny):
+    good = lbm.params(4, 0.7, 64, 64, kappa=0.1, tau=1.0, k=0.2)
+    bad = lbm.params(4, 0.7, nx, ny, kappa=0.1, tau=1.0, k=0.2)
+    st, msg = _batch_status([good, bad], [np.full((64, 64), 0.1), np.full((ny, nx), 0.1)])
+    assert st == lbm.LBM_E_INVALID and "simulation 1" in msg
+
+
+def test_batch_validates_each_simulation():
+    good = lbm.params(4, 0.7, 64, 64, kappa=0.1, tau=1.0, k=0.2)
+    bad = lbm.params(4, 0.7, 64, 64, kappa=0.1, tau=0.4, k=0.2)
+    st, msg = _batch_status([good, bad, good], [np.full((64, 64), 0.1)] * 3)
+    assert st == lbm.LBM_E_INVALID and "simulation 1" in msg and "tau" in msg
+    rho = np.full((64, 64), 0.1)
+    rho[1, 2] = -1.0
+    st, msg = _batch_status([good, good], [np.full((64, 64), 0.1), rho])
+    assert st == lbm.LBM_E_DOMAIN and "simulation 1" in msg
+    st, _ = _batch_status([], [])
+    assert st == lbm.LBM_E_INVALID
