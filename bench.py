@@ -10,9 +10,11 @@ One "step" is one lattice-Boltzmann time step of the whole mesh (the three
 kernels of the solver).  Prints one JSON line with MLUPS (whole job), the
 roofline entry of the dominant kernel (algorithmic bytes / its average
 duration, HIP events on the solver's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload.  The "sweep" entry times a batched
+sweep of simulations of uneven size to convergence against running each on
+its own (the plain method).
 
-    python bench.py [--gpus 1] [--steps 20000] [--warmup 200]
+    python bench.py [--gpus 1] [--steps 20000] [--warmup 200] [--sweep small|full|none]
 """
 import argparse
 import json
@@ -63,18 +65,110 @@ def measured_traffic(kernel):
     return t["bytes_per_launch"].get(kernel)
 
 
+# Batched sweep (Sec. 5.1 coexistence curve, Sec. 5.3 Laplace's law): square
+# periodic CS meshes, half flat slabs, half static drops, T/Tc uniform in
+# [0.35, 0.95], each run until max |rho(t) - rho(t - 100)| < 1e-12.
+SWEEP = dict(seed=4, kappa=0.1, k=0.2, tau=1.0, width=5.0, tol=1e-12, check_every=100,
+             max_steps=3_000_000)
+SWEEP_SETS = {"small": dict(count=16, sizes=(64, 128, 256)),
+              "full": dict(count=64, sizes=(64, 128, 256, 512))}
+
+
+def sweep_cases(lbm, inputs, which):
+    cfg = SWEEP_SETS[which]
+    members = inputs.sweep_members(SWEEP["seed"], cfg["count"], sizes=cfg["sizes"])
+    cases = []
+    for m in members:
+        n = m["n"]
+        p = lbm.params(lbm.EOS_CS, m["T_r"], n, n, kappa=SWEEP["kappa"], tau=SWEEP["tau"],
+                       k=SWEEP["k"])
+        g, l = lbm.maxwell(p)
+        if m["kind"] == "slab":
+            rho0, _, _ = inputs.slab(n, n, g, l, SWEEP["width"])
+        else:
+            rho0, _, _ = inputs.droplet(n, n, g, l, m["radius"], SWEEP["width"])
+        cases.append((m, p, rho0))
+    return cases
+
+
+def sweep_bench(lbm, inputs, which):
+    """Time to converge every member: one batch (graph-replayed chunks,
+    autotuned column shape) against one context per member run one after the
+    other (the plain method).  Each plain run uses the batch's column-pass
+    chunk, so both evolve bitwise alike and take the same steps."""
+    import torch
+    cases = sweep_cases(lbm, inputs, which)
+    n = len(cases)
+    tol, every, cap = SWEEP["tol"], SWEEP["check_every"], SWEEP["max_steps"]
+    b = lbm.Batch([c[1] for c in cases], [c[2] for c in cases])
+    tune = b.autotune(10)
+    col_elems, chunk = min(tune, key=tune.get)
+    print("sweep %s: %d members, batch column shape %s" % (which, n, (col_elems, chunk)),
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, part = 0, 100_000
+    while done < cap:
+        st, _, _, sts = b.run_until_converged(tol, every, min(part, cap - done), use_graph=True)
+        done += part
+        active = sum(1 for x in sts if x == lbm.LBM_NOT_CONVERGED)
+        print("  batch: %d steps, %d active, %.1f s" % (done, active, time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+        if active == 0:
+            break
+    t_batch = time.perf_counter() - t0
+    steps_b = [b.steps_taken(i) for i in range(n)]
+    status_b = list(sts)
+    b.close()
+
+    t_seq, steps_s, status_s = 0.0, [], []
+    for i, (m, p, rho0) in enumerate(cases):
+        s = lbm.Solver(p, rho0)
+        s.set_column_shape(col_elems // p.ny, chunk)
+        s.synchronize()
+        t0 = time.perf_counter()
+        st, k, _ = s.run_until_converged(tol, every, cap)
+        s.synchronize()
+        t_seq += time.perf_counter() - t0
+        steps_s.append(k)
+        status_s.append(st)
+        s.close()
+        if i % 8 == 7 or i == n - 1:
+            print("  plain: %d of %d done, %.1f s" % (i + 1, n, t_seq), file=sys.stderr,
+                  flush=True)
+    lups = sum(c[1].nx * c[1].ny * k for c, k in zip(cases, steps_b))
+    return {
+        "set": which, "members": n, "sizes": list(SWEEP_SETS[which]["sizes"]),
+        "eos": "CS", "T_r_range": [0.35, 0.95], "kappa": SWEEP["kappa"], "k": SWEEP["k"],
+        "tau": SWEEP["tau"], "tol": tol, "check_every": every,
+        "batched_s": round(t_batch, 3), "plain_sequential_s": round(t_seq, 3),
+        "speedup": round(t_seq / t_batch, 3),
+        "all_converged": all(x == lbm.LBM_OK for x in status_b),
+        "same_steps_as_plain": steps_b == steps_s and status_b == status_s,
+        "steps_min_max": [min(steps_b), max(steps_b)],
+        "lattice_updates": lups,
+        "batched_MLUPS": round(lups / t_batch / 1e6, 1),
+        "plain_MLUPS": round(lups / t_seq / 1e6, 1),
+        "column_shape": [col_elems, chunk],
+    }
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
 
 
-def cpu_baseline(rho0, ux0, uy0, budget_s=15.0):
+def cpu_baseline(budget_s=15.0):
     """The oracle on the host, single thread, on the first steps of the same
-    workload until about `budget_s` of CPU work."""
+    workload until about `budget_s` of CPU work.  Its inputs are built from
+    the oracle's own coexistence densities."""
     import oracle
     from oracle import analytic as A
+    from paper_1906_09530_amd import inputs
     op = A.params(A.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"], k=CFG["k"],
                   mu_cap=CFG["mu_cap"])
+    g, l = (float(v) for v in A.EOS(A.EOS_PR).maxwell(CFG["T_r"]))
+    rho0, ux0, uy0 = inputs.droplet(NX, NY, g, l, CFG["radius"], CFG["width"])
     f = oracle.init(op, rho0, ux0, uy0)
     steps = 0
     t0 = time.perf_counter()
@@ -97,6 +191,9 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=1000,
                     help="steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", choices=["small", "full", "none"], default="small",
+                    help="batched sweep vs one run per member (time to converge): 16 members "
+                         "up to 256^2 (small), 64 members up to 512^2 (full, minutes), or none")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, to calibrate FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -167,7 +264,8 @@ def main():
     s.close()
 
     traffic = measured_traffic(PASS_NAMES[dom])
-    cpu = None if args.no_cpu_baseline else cpu_baseline(rho0, ux0, uy0)
+    sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -210,6 +308,7 @@ def main():
         "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
                   "rho_corner": float(outside), "max_speed": float(np.hypot(vx, vy).max()),
                   "rho_g_maxwell": rho_g, "rho_l_maxwell": rho_l},
+        "sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -12,6 +12,8 @@ digits, so that none of it depends on FP64 rounding:
 * the planar-interface profile (Eqs. 22-24), interface width and surface
   tension, and their transformation to the mesh space (Sec. 4.1, Eq. 33).
 """
+import functools
+
 import mpmath as mp
 
 from .lib import EOS_CS, EOS_PR, EOS_RK, EOS_RKS, EOS_VDW, OracleParams
@@ -251,3 +253,11 @@ def params(eos, T_r, nx, ny, *, kappa, tau, k, mu_cap=float("inf"), cfd_alpha=1.
     return OracleParams(nx=nx, ny=ny, bc_y=bc_y, eos=eos, wall_ux=wall_ux, a=float(e.a),
                         b=float(e.b), R=float(e.R), T=float(T), alpha_T=float(al),
                         kappa=kappa, tau=tau, k=k, mu_cap=mu_cap, cfd_alpha=cfd_alpha)
+
+
+@functools.lru_cache(maxsize=None)
+def coexistence(eos, T_r, omega=None):
+    """Maxwell coexistence densities (rho_g, rho_l) as doubles, for the
+    default constants of each EOS (Sec. 3.2): inputs of seeded test fields."""
+    g, l = EOS(eos, omega=OMEGA_WATER if omega is None else omega).maxwell(T_r)
+    return float(g), float(l)

@@ -96,3 +96,25 @@ def splash(nx, ny, rho_g, rho_l, radius, width, *, film=40, drop_center=None, dr
     ux = np.full_like(rho, frame_ux)
     uy = np.where(phi_drop > 0.5, drop_uy, 0.0)
     return np.ascontiguousarray(rho), ux, np.ascontiguousarray(uy)
+
+
+SWEEP_SIZES = (64, 128, 256, 512)
+
+
+def sweep_members(seed, count, *, sizes=SWEEP_SIZES, t_lo=0.35, t_hi=0.95, r_lo=0.15,
+                  r_hi=0.35):
+    """Members of a batched sweep: square periodic meshes of side drawn
+    uniformly from `sizes`, the first half flat slabs and the second half
+    static drops of radius r N with r uniform in [r_lo, r_hi), each at a
+    reduced temperature uniform in [t_lo, t_hi).  Returns a list of dicts
+    {"kind", "n", "T_r", "radius"} (radius None for slabs).  Three draws per
+    member from stream `seed`: size, temperature, radius."""
+    u = uniform01(seed, 3 * count).reshape(count, 3)
+    out = []
+    for i in range(count):
+        n = sizes[min(int(u[i, 0] * len(sizes)), len(sizes) - 1)]
+        T_r = t_lo + (t_hi - t_lo) * float(u[i, 1])
+        drop = i >= count // 2
+        radius = (r_lo + (r_hi - r_lo) * float(u[i, 2])) * n if drop else None
+        out.append({"kind": "drop" if drop else "slab", "n": n, "T_r": T_r, "radius": radius})
+    return out

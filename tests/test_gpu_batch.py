@@ -20,20 +20,20 @@ TOL = 1e-10
 
 def _slab(T_r, nx, ny, k):
     p = lbm.params(lbm.EOS_CS, T_r, nx, ny, kappa=0.1, tau=1.0, k=k)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     return p, inputs.slab(nx, ny, g, l, 4.0)
 
 
 def _pr_drop(nx, ny, seed):
     p = lbm.params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     return p, inputs.droplet(nx, ny, g, l, min(nx, ny) / 4.0, 5.0, seed=seed, noise=1e-6)
 
 
 def _splash(nx, ny, frame):
     p = lbm.params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0, bc_y=1,
                    wall_ux=frame)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     return p, inputs.splash(nx, ny, g, l, radius=16.0, width=5.0, film=12, drop_uy=-0.05,
                             frame_ux=frame)
 
@@ -148,7 +148,7 @@ def test_nonfinite_simulation_is_retired_alone():
     its own."""
     n = 64
     p = lbm.params(lbm.EOS_PR, 0.5, n, n, kappa=0.1, tau=0.8, k=0.5, mu_cap=6.0)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     bad = (p, inputs.droplet(n, n, g, l, 20.0, 10.0))
     good = _slab(0.8, 64, 64, 0.3)
     b = _batch([bad, good])

@@ -79,7 +79,7 @@ def test_small_periodic_drop_cs_fourth_order(seed):
     (measured: 8e-14, 9e-13, 1.3e-11, 1.7e-10 at 500..2000 steps); beyond
     1000 steps the bound follows that growth: 1e-9 at 1500, 1e-8 at 2000."""
     p, op = _case_params(lbm.EOS_CS, 0.7, 64, 64, kappa=0.0, tau=1.0, k=1.0, cfd_alpha=0.25)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(64, 64, g, l, 16.0, 4.0, seed=seed, noise=1e-6)
     _run_case("cs64-seed%d" % seed, p, op, rho0, ux0, uy0, [500, 1000, 1500, 2000],
               tol={1500: (1e-9, 1e-9), 2000: (1e-8, 1e-8)})
@@ -89,7 +89,7 @@ def test_ragged_tiles_pr_drop_with_limit():
     """300 x 200 (row blocks of 13 rows, column blocks of 20 columns, ragged
     tails in both), PR at T_r = 0.6, sixth-order scheme, upper limit 6."""
     p, op = _case_params(lbm.EOS_PR, 0.6, 300, 200, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(300, 200, g, l, 50.0, 5.0, seed=7, noise=1e-6,
                                     center=(140.0, 95.0))
     _run_case("pr300x200", p, op, rho0, ux0, uy0, [100, 300])
@@ -102,7 +102,7 @@ def test_general_reduction_path(walls):
     nx, ny = 98, 66
     p, op = _case_params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0,
                          bc_y=walls)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 18.0, 5.0, seed=11, noise=1e-6)
     _run_case("general98x66-walls%d" % walls, p, op, rho0, ux0, uy0, [50, 200])
 
@@ -115,7 +115,7 @@ def test_every_column_shape_matches_oracle(walls):
     nx, ny = 128, 256
     p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 30.0, 4.0, seed=12, noise=1e-4,
                                     center=(60.0, 120.0))
     f = oracle.init(op, rho0, ux0, uy0)
@@ -150,7 +150,7 @@ def test_walls_splash_moving_frame(frame):
     nx, ny = 160, 96
     p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0,
                          bc_y=1, wall_ux=frame)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, radius=16.0, width=5.0, film=12,
                                    drop_uy=-0.05, frame_ux=frame)
     _run_case("splash-frame%.2f" % frame, p, op, rho0, ux0, uy0, [150, 400])
@@ -159,7 +159,7 @@ def test_walls_splash_moving_frame(frame):
 def test_flat_slab_parity_and_zero_tangential_velocity():
     nx, ny = 16, 128
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=1.0, k=0.2)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 4.0)
     _run_case("slab", p, op, rho0, ux0, uy0, [500])
     s = lbm.Solver(p, rho0, ux0, uy0)
@@ -172,7 +172,7 @@ def test_flat_slab_parity_and_zero_tangential_velocity():
 def test_extreme_shapes(nx, ny):
     """Smallest mesh and the longest rows/columns a block holds."""
     p, op = _case_params(lbm.EOS_CS, 0.8, nx, ny, kappa=0.1, tau=1.0, k=0.2)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, min(nx, ny) / 4.0, 2.0, seed=5, noise=1e-3)
     _run_case("shape%dx%d" % (nx, ny), p, op, rho0, ux0, uy0, [30])
 
@@ -183,7 +183,7 @@ def test_force_fields_match_oracle(walls):
     nx, ny = 200, 136
     p, op = _case_params(lbm.EOS_PR, 0.5, nx, ny, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0,
                          bc_y=walls)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 40.0, 8.0, seed=9, noise=1e-6,
                                     center=(90.0, 60.0))
     s = lbm.Solver(p, rho0, ux0, uy0)
@@ -203,13 +203,13 @@ def test_full_size_one_step(name):
     if name == "pr1024":
         n = 1024
         p, op = _case_params(lbm.EOS_PR, 0.5, n, n, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0)
-        g, l = lbm.maxwell(p)
+        g, l = A.coexistence(p.eos, p.T_r)
         rho0, ux0, uy0 = inputs.droplet(n, n, g, l, 200.0, 10.0, seed=1, noise=1e-6)
     else:
         nx, ny = 4096, 2048
         p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0,
                              bc_y=1)
-        g, l = lbm.maxwell(p)
+        g, l = A.coexistence(p.eos, p.T_r)
         rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, radius=100.0, width=5.0, film=40,
                                        drop_uy=-0.05)
     _run_case(name, p, op, rho0, ux0, uy0, [1])
@@ -218,7 +218,7 @@ def test_full_size_one_step(name):
 def test_run_until_converged_matches_oracle():
     nx, ny = 8, 64
     p, op = _case_params(lbm.EOS_CS, 0.8, nx, ny, kappa=0.1, tau=1.0, k=0.3)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 4.0)
     s = lbm.Solver(p, rho0, ux0, uy0)
     st, steps, delta = s.run_until_converged(1e-11, 100, 200000)
@@ -242,7 +242,7 @@ def test_nonfinite_is_detected_and_sticky():
     outrun the explicit step); the divergence is reported, not hidden."""
     n = 64
     p, _ = _case_params(lbm.EOS_PR, 0.5, n, n, kappa=0.1, tau=0.8, k=0.5, mu_cap=6.0)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(n, n, g, l, 20.0, 10.0)
     s = lbm.Solver(p, rho0, ux0, uy0)
     with pytest.raises(lbm.LBMError) as ei:
@@ -255,7 +255,7 @@ def test_nonfinite_is_detected_and_sticky():
 def test_checkpoint_resume_and_determinism_bitwise():
     nx, ny = 96, 64
     p, _ = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.7, k=0.2)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 15.0, 4.0, seed=2, noise=1e-4)
     a = lbm.Solver(p, rho0, ux0, uy0)
     a.step(60)
@@ -277,7 +277,7 @@ def test_device_buffers_and_workspace():
     import torch
     nx, ny = 80, 72
     p, _ = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=1.0, k=0.2)
-    g, l = lbm.maxwell(p)
+    g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 15.0, 4.0, seed=4, noise=1e-5)
     a = lbm.Solver(p, rho0, ux0, uy0)
     a.step(40)
