@@ -12,7 +12,10 @@ Two parts:
   ``liboracle.so`` and reached here through ctypes;
 * ``analytic.py`` -- thermodynamics in arbitrary precision (mpmath): critical
   points, the Maxwell construction, the planar-interface profile and surface
-  tension.
+  tension;
+* ``mlp.py`` -- the learned warm start in FP64 (numpy): the network, its
+  backpropagated gradient, Adam, bfloat16 inference and the warm-start
+  density field.
 """
 from .lib import (  # noqa: F401
     EOS_CS, EOS_PR, EOS_RK, EOS_RKS, EOS_VDW, OracleParams, build, cfm_line, collide_node,
