@@ -118,3 +118,38 @@ def sweep_members(seed, count, *, sizes=SWEEP_SIZES, t_lo=0.35, t_hi=0.95, r_lo=
         radius = (r_lo + (r_hi - r_lo) * float(u[i, 2])) * n if drop else None
         out.append({"kind": "drop" if drop else "slab", "n": n, "T_r": T_r, "radius": radius})
     return out
+
+
+def warmstart_members(seed, count, *, t_lo, t_hi, r_lo, r_hi, k_lo, k_hi):
+    """Static drops for the learned warm start: reduced temperature, radius
+    fraction of the mesh side and mesh coefficient k, each uniform in its
+    range; three draws per member from stream `seed`.  Returns a list of
+    dicts {"T_r", "r_frac", "k"}."""
+    u = uniform01(seed, 3 * count).reshape(count, 3)
+    return [{"T_r": t_lo + (t_hi - t_lo) * float(a), "r_frac": r_lo + (r_hi - r_lo) * float(b),
+             "k": k_lo + (k_hi - k_lo) * float(c)} for a, b, c in u]
+
+
+def network_init(seed, n_in=5, n_hid=128):
+    """Initial parameters of the n_in-n_hid-n_hid-1 network in the flat order
+    W1, b1, W2, b2, W3, b3: weights uniform in +-sqrt(6 / (fan_in + fan_out))
+    (Glorot and Bengio, 2010), biases zero; float32."""
+    shapes = [(n_hid, n_in), (n_hid,), (n_hid, n_hid), (n_hid,), (1, n_hid), (1,)]
+    total = sum(int(np.prod(s)) for s in shapes)
+    u = 2.0 * uniform01(seed, total) - 1.0
+    out, o = [], 0
+    for s in shapes:
+        n = int(np.prod(s))
+        if len(s) == 2:
+            out.append(u[o:o + n] * np.sqrt(6.0 / (s[0] + s[1])))
+        else:
+            out.append(np.zeros(n))
+        o += n
+    return np.concatenate(out).astype(np.float32)
+
+
+def minibatch_order(seed, nsamples, batch, iters):
+    """iters * batch sample indices drawn uniformly (with replacement) from
+    [0, nsamples), int32."""
+    u = uniform01(seed, batch * iters)
+    return np.minimum((u * nsamples).astype(np.int64), nsamples - 1).astype(np.int32)

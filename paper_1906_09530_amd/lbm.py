@@ -98,6 +98,17 @@ def load():
         "lbm_batch_steps": (i64, [P, i32]),
         "lbm_batch_destroy": (None, [P]),
         "lbm_batch_last_error": (C.c_char_p, [P]),
+        "lbm_mlp_create": (i32, [P, P, C.POINTER(P)]),
+        "lbm_mlp_get_params": (i32, [P, P]),
+        "lbm_mlp_set_params": (i32, [P, P]),
+        "lbm_mlp_forward": (i32, [P, P, i64, P, i32]),
+        "lbm_mlp_loss_grad": (i32, [P, P, P, i64, C.POINTER(C.c_float), P]),
+        "lbm_mlp_train": (i32, [P, P, P, i64, P, i64, i64, C.c_float, C.c_float, C.c_float,
+                                C.c_float, P]),
+        "lbm_mlp_steps": (i64, [P]),
+        "lbm_warm_start_drop": (i32, [P, pp, d, d, d, d, P]),
+        "lbm_mlp_destroy": (None, [P]),
+        "lbm_mlp_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -333,3 +344,95 @@ class Batch:
         f = np.empty((9, p.ny, p.nx))
         _bcheck(load().lbm_batch_get_state(self.b, int(sim), f.ctypes.data), self.b)
         return f
+
+
+MLP_PARAMS = 17409
+
+
+def _mcheck(st, m=None, ok=(LBM_OK,)):
+    if st not in ok:
+        raise LBMError(st, load().lbm_mlp_last_error(m).decode())
+    return st
+
+
+def _dev_ptr(a, dtype):
+    import torch
+    assert a.is_cuda and a.dtype == dtype and a.is_contiguous()
+    return a.data_ptr()
+
+
+class MLP:
+    """The warm-start network (an lbm_mlp): FP32 parameters on the device,
+    trained and evaluated by the library's kernels.  Samples and targets are
+    torch device tensors (float32); parameters and gradients cross as numpy
+    float32 arrays."""
+
+    def __init__(self, params, stream=None):
+        lib = load()
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.shape == (MLP_PARAMS,)
+        m = C.c_void_p()
+        _mcheck(lib.lbm_mlp_create(params.ctypes.data, stream, C.byref(m)), None)
+        self.m = m
+
+    def close(self):
+        if getattr(self, "m", None):
+            load().lbm_mlp_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _mcheck(load().lbm_mlp_get_params(self.m, out.ctypes.data), self.m)
+        return out
+
+    def set_params(self, params):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        _mcheck(load().lbm_mlp_set_params(self.m, params.ctypes.data), self.m)
+
+    def forward(self, x, bf16=False):
+        import torch
+        n = x.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        _mcheck(load().lbm_mlp_forward(self.m, _dev_ptr(x, torch.float32), n,
+                                       _dev_ptr(y, torch.float32), int(bool(bf16))), self.m)
+        return y
+
+    def loss_grad(self, x, t):
+        import torch
+        loss = C.c_float()
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        _mcheck(load().lbm_mlp_loss_grad(self.m, _dev_ptr(x, torch.float32),
+                                         _dev_ptr(t, torch.float32), x.shape[0], C.byref(loss),
+                                         g.ctypes.data), self.m)
+        return loss.value, g
+
+    def train(self, x, t, order, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """Adam steps over consecutive minibatches of `order` (device int32,
+        a multiple of batch long); returns the per-step losses."""
+        import torch
+        iters = order.shape[0] // batch
+        losses = np.empty(iters, dtype=np.float32)
+        _mcheck(load().lbm_mlp_train(self.m, _dev_ptr(x, torch.float32),
+                                     _dev_ptr(t, torch.float32), x.shape[0],
+                                     _dev_ptr(order, torch.int32), batch, iters, lr, beta1,
+                                     beta2, eps, losses.ctypes.data), self.m)
+        return losses
+
+    @property
+    def steps(self):
+        return load().lbm_mlp_steps(self.m)
+
+    def warm_start_drop(self, p, radius, target_mass, center=None):
+        """Warm-start density (device tensor (ny, nx), float64) of a drop."""
+        import torch
+        cx, cy = (p.nx / 2.0, p.ny / 2.0) if center is None else center
+        rho = torch.empty((p.ny, p.nx), dtype=torch.float64, device="cuda")
+        _mcheck(load().lbm_warm_start_drop(self.m, C.byref(p), cx, cy, radius, target_mass,
+                                           _dev_ptr(rho, torch.float64)), self.m)
+        return rho
