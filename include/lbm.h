@@ -154,6 +154,14 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
  * count are not changed.  Synchronises the stream. */
 lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
 
+/* Give the fluid the velocity (vx, vy) (arrays of nx*ny, host or device per
+ * src_on_device; NULL for zero): the state becomes f = feq(rho, u) with rho
+ * the current density and u = v - F/(2 rho), F the force of Eq. 12 of that
+ * density, so that the velocity v of Sec. 2 (the observed velocity
+ * u + F/(2 rho), Eq. 5) equals the given one.  With NULL, the fluid starts
+ * at rest in that sense rather than with zero bare velocity.  Synchronises. */
+lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int src_on_device);
+
 /* Autotuner: time the column pass of the current state for each strip width
  * (columns per workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS
  * holds and, for the factorised solve, each chunk length (column nodes per
@@ -242,6 +250,9 @@ lbm_status lbm_batch_run_until_converged(lbm_batch *b, double tol, int64_t check
  * be NULL); the state f[9][ny][nx] of simulation sim (host).  Synchronise. */
 lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx, double *vy);
 lbm_status lbm_batch_get_state(lbm_batch *b, int32_t sim, double *f);
+
+/* lbm_set_velocity for simulation sim (host arrays, NULL for zero). */
+lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, const double *vy);
 
 /* Steps taken by simulation sim (-1 for an invalid index). */
 int64_t lbm_batch_steps(const lbm_batch *b, int32_t sim);

@@ -2,31 +2,38 @@
  * lbm_warmstart.h -- C ABI of the learned warm start of libcplbm.
  *
  * The paper initialises a static drop with a tanh profile between the
- * Maxwell densities (Sec. 5.3, Eq. 41).  This extension proposes the initial
- * density with a small network instead, trained on converged drops that the
- * solver itself produced, so that the solver reaches its convergence
- * criterion in fewer steps.  The solver, its criterion and its converged
- * fields are unchanged: the network only chooses the starting point, and
- * the tanh start remains available as the fallback.
+ * Maxwell densities and zero velocity (Sec. 5.3, Eq. 41).  This extension
+ * proposes the initial density and velocity with a small network instead,
+ * trained on converged drops that the solver itself produced, so that the
+ * solver reaches its convergence criterion in fewer steps.  The velocity
+ * matters: a drop relaxes towards a steady state that carries the small
+ * parasitic currents of the discretisation, and a start at rest takes as
+ * long to build them up as the tanh start does, whatever its density.  The
+ * solver, its criterion and its converged fields are unchanged: the network
+ * only chooses the starting point, and the tanh start remains the fallback.
  *
  * Network (FP32 parameters, one flat array of LBM_MLP_PARAMS floats, in this
- * order): W1 [128][5], b1 [128], W2 [128][128], b2 [128], W3 [128], b3 [1];
- *     a1 = tanh(W1 x + b1), a2 = tanh(W2 a1 + b2), y = W3 . a2 + b3.
- * Training minimises mean (y - t)^2 with Adam (Kingma and Ba, ICLR 2015,
- * bias-corrected moments), FP32 throughout.  Inference runs either in FP32
- * or with the 128 x 128 product in bfloat16 on the matrix cores (FP32
- * accumulation; bfloat16 = binary32 rounded to nearest, ties to even, upper
- * 16 bits).
+ * order): W1 [128][7], b1 [128], W2 [128][128], b2 [128], W3 [3][128], b3 [3];
+ *     a1 = tanh(W1 x + b1), a2 = tanh(W2 a1 + b2), y = W3 a2 + b3.
+ * Training minimises the mean over samples of sum_j (y_j - t_j)^2 with Adam
+ * (Kingma and Ba, ICLR 2015, bias-corrected moments), FP32 throughout.
+ * Inference runs either in FP32 or with the 128 x 128 product in bfloat16 on
+ * the matrix cores (FP32 accumulation; bfloat16 = binary32 rounded to
+ * nearest, ties to even, upper 16 bits).
  *
  * Warm-start features of a node of a drop of radius R centred at (cx, cy):
- * f = (T/Tc, R / 256, kappa, k, r - R), r the plain distance to the centre
- * in mesh nodes, normalised as x_i = (f_i - c_i) / s_i with
- * c = (0.5, 0.25, 0.1, 0.25, 0) and s = (0.25, 0.1, 0.1, 0.1, 8).  The
- * output is the normalised log density
- *     y = (ln rho - ln rho_g) / (ln rho_l - ln rho_g),
- * (rho_g, rho_l) the Maxwell pair at T (Sec. 5.1).
+ * f = (T/Tc, R / 256, kappa, k, r - R, cos 4 theta, sin 4 theta), r the plain
+ * distance to the centre in mesh nodes and theta the polar angle about it
+ * (0 at the centre), normalised as x_i = (f_i - c_i) / s_i with
+ * c = (0.5, 0.25, 0.1, 0.25, 0, 0, 0) and s = (0.25, 0.1, 0.1, 0.1, 8, 1, 1).
+ * The angle enters as 4 theta: a drop centred in a square periodic mesh
+ * keeps the square's symmetry.  Outputs: the normalised log density
+ *     y0 = (ln rho - ln rho_g) / (ln rho_l - ln rho_g),
+ * (rho_g, rho_l) the Maxwell pair at T (Sec. 5.1), and the radial and
+ * azimuthal fluid velocity in units of 1e-3, y1 = 1e3 v_r, y2 = 1e3 v_theta
+ * (v = u + F/(2 rho), the velocity the solver reports, Eq. 5).
  *
- * Memory: x, t, y, order and rho arguments are device pointers; params,
+ * Memory: x, t, y, order, rho, ux and uy arguments are device pointers; params,
  * grad and losses are host pointers.  Work is enqueued on the stream given
  * at creation (NULL: the default stream); calls that return host data
  * synchronise it.  Errors as in lbm.h; lbm_mlp_last_error() explains.
@@ -42,7 +49,7 @@
 extern "C" {
 #endif
 
-#define LBM_MLP_PARAMS 17409
+#define LBM_MLP_PARAMS 17923
 
 typedef struct lbm_mlp lbm_mlp;
 
@@ -55,12 +62,12 @@ lbm_status lbm_mlp_create(const float *params, void *hip_stream, lbm_mlp **out);
 lbm_status lbm_mlp_get_params(lbm_mlp *m, float *params);
 lbm_status lbm_mlp_set_params(lbm_mlp *m, const float *params);
 
-/* y[n] = network(x[n][5]) on the device; bf16 != 0 takes the matrix-core
+/* y[n][3] = network(x[n][7]) on the device; bf16 != 0 takes the matrix-core
  * path.  Not synchronised. */
 lbm_status lbm_mlp_forward(lbm_mlp *m, const float *x, int64_t n, float *y, int bf16);
 
-/* Mean squared error over samples (x[n][5], t[n]) and its gradient with
- * respect to the parameters (host outputs, either may be NULL). */
+/* Loss over samples (x[n][7], t[n][3]) and its gradient with respect to the
+ * parameters (host outputs, either may be NULL). */
 lbm_status lbm_mlp_loss_grad(lbm_mlp *m, const float *x, const float *t, int64_t n, float *loss,
                              float *grad);
 
@@ -78,15 +85,24 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t nsa
 /* Adam steps taken since creation or the last set_params. */
 int64_t lbm_mlp_steps(const lbm_mlp *m);
 
-/* Warm-start density of a static drop (radius, centre (cx, cy) in mesh
+/* Warm-start fields of a static drop (radius, centre (cx, cy) in mesh
  * nodes) for the parameters p (periodic mesh, any EOS; features use p->T_r,
- * p->kappa, p->k): rho (device, ny*nx doubles, layout of lbm.h) from the
- * bfloat16 network, then mass matched: target_mass - sum(rho) is added in
- * proportion to max((rho - rho_g)(rho_l - rho), 0), which vanishes in both
- * bulks, so that sum(rho) = target_mass to round-off.  Pass it to lbm_init
- * with src_on_device = 1.  Not synchronised. */
+ * p->kappa, p->k), from the network (bf16 != 0: matrix-core inference, else
+ * FP32): rho (device, ny*nx doubles, layout of lbm.h), mass matched --
+ * target_mass - sum(rho) is added in proportion to
+ * max((rho - rho_g)(rho_l - rho), 0), which vanishes in both bulks, so that
+ * sum(rho) = target_mass to round-off -- and the fluid velocity v (ux, uy:
+ * device, ny*nx doubles each, both NULL to skip).  Start a solver from rho
+ * (lbm_init or lbm_batch_create) and then give it v with lbm_set_velocity or
+ * lbm_batch_set_velocity.  The network is evaluated at each node and at its
+ * mirror features (sin 4 theta negated) and the fields are symmetrised --
+ * density and radial velocity even, azimuthal velocity odd under the
+ * square's reflections -- so that the proposal carries no net momentum and
+ * keeps its centre.  LBM_E_DOMAIN when the matched density would not be
+ * positive (the caller then falls back to the tanh start).  Synchronises. */
 lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, double cy,
-                               double radius, double target_mass, double *rho);
+                               double radius, double target_mass, int bf16, double *rho,
+                               double *ux, double *uy);
 
 void lbm_mlp_destroy(lbm_mlp *m);
 

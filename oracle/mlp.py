@@ -1,6 +1,6 @@
-"""FP64 reference of the learned warm start: a 5-128-128-1 tanh network, its
-loss gradient, the Adam update, bfloat16 inference and the warm-start density
-field built from it.
+"""FP64 reference of the learned warm start: a 7-128-128-3 tanh network, its
+loss gradient, the Adam update, bfloat16 inference and the warm-start fields
+(density and velocity) built from it.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -10,28 +10,36 @@ reaches its converged state in fewer steps.  What it computes follows
 published definitions:
 
 * the network: z1 = W1 x + b1, a1 = tanh z1, z2 = W2 a1 + b2, a2 = tanh z2,
-  y = W3 a2 + b3, loss = mean over samples of (y - t)^2;
+  y = W3 a2 + b3 (three outputs), loss = mean over samples of
+  sum_j (y_j - t_j)^2;
 * gradients by the chain rule (backpropagation), written out layer by layer;
 * Adam (Kingma and Ba, ICLR 2015, Algorithm 1) with bias correction;
 * bfloat16 = the upper 16 bits of an IEEE binary32 after rounding to
   nearest, ties to even.
 
 Flat parameter vector (float32 on the device, float64 here), in this order:
-W1 (128 x 5, row = output unit), b1 (128), W2 (128 x 128), b2 (128),
-W3 (128), b3 (1): 17 409 values.
+W1 (128 x 7, row = output unit), b1 (128), W2 (128 x 128), b2 (128),
+W3 (3 x 128), b3 (3): 17 923 values.
+
+Features of a node of a drop: (T/Tc, R / 256, kappa, k, r - R, cos 4 theta,
+sin 4 theta), theta the polar angle about the drop's centre.  Outputs: the
+normalised log density (ln rho - ln rho_g) / (ln rho_l - ln rho_g) and the
+radial and azimuthal fluid velocity v = u + F/(2 rho) in units of 1e-3.  The angle enters through
+4 theta because a drop centred in a square periodic mesh keeps the square's
+symmetry, and so does its steady velocity field.
 """
 import numpy as np
 
-N_IN, N_HID = 5, 128
+N_IN, N_HID, N_OUT = 7, 128, 3
 SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
-          ("W3", (N_HID,)), ("b3", (1,))]
+          ("W3", (N_OUT, N_HID)), ("b3", (N_OUT,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 
-# feature normalisation: x_i = (f_i - CENTER_i) / SCALE_i for the features
-# (T/Tc, R / 256, kappa, k, r - R)
-FEATURE_CENTER = np.array([0.5, 0.25, 0.1, 0.25, 0.0])
-FEATURE_SCALE = np.array([0.25, 0.1, 0.1, 0.1, 8.0])
+# feature normalisation: x_i = (f_i - CENTER_i) / SCALE_i
+FEATURE_CENTER = np.array([0.5, 0.25, 0.1, 0.25, 0.0, 0.0, 0.0])
+FEATURE_SCALE = np.array([0.25, 0.1, 0.1, 0.1, 8.0, 1.0, 1.0])
 R_REF = 256.0
+U_SCALE = 1e-3
 
 
 def unpack(w):
@@ -45,16 +53,16 @@ def unpack(w):
 
 
 def forward(w, x):
-    """y (n,) and the activations (a1, a2) for samples x (n, 5)."""
+    """y (n, 3) and the activations (a1, a2) for samples x (n, 7)."""
     W1, b1, W2, b2, W3, b3 = unpack(np.asarray(w, dtype=np.float64))
     a1 = np.tanh(x @ W1.T + b1)
     a2 = np.tanh(a1 @ W2.T + b2)
-    return a2 @ W3 + b3[0], a1, a2
+    return a2 @ W3.T + b3, a1, a2
 
 
 def loss(w, x, t):
     y, _, _ = forward(w, x)
-    return float(np.mean((y - t) ** 2))
+    return float(np.sum((y - t) ** 2) / x.shape[0])
 
 
 def grad(w, x, t):
@@ -62,17 +70,17 @@ def grad(w, x, t):
     W1, b1, W2, b2, W3, b3 = unpack(np.asarray(w, dtype=np.float64))
     y, a1, a2 = forward(w, x)
     n = x.shape[0]
-    dy = 2.0 * (y - t) / n                # dL/dy
-    gW3 = dy @ a2                         # dL/dW3[j] = sum_s dy_s a2[s, j]
-    gb3 = np.array([dy.sum()])
-    dz2 = np.outer(dy, W3) * (1.0 - a2 * a2)   # through y = W3 a2 and tanh
+    dy = 2.0 * (y - t) / n                # dL/dy, (n, 3)
+    gW3 = dy.T @ a2                       # dL/dW3[j, u] = sum_s dy[s, j] a2[s, u]
+    gb3 = dy.sum(axis=0)
+    dz2 = (dy @ W3) * (1.0 - a2 * a2)     # through y = W3 a2 and tanh
     gW2 = dz2.T @ a1
     gb2 = dz2.sum(axis=0)
     dz1 = (dz2 @ W2) * (1.0 - a1 * a1)
     gW1 = dz1.T @ x
     gb1 = dz1.sum(axis=0)
-    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3, gb3])
-    return float(np.mean((y - t) ** 2)), g
+    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+    return float(np.sum((y - t) ** 2) / n), g
 
 
 def adam(w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -101,24 +109,70 @@ def forward_bf16(w, x):
     W1, b1, W2, b2, W3, b3 = unpack(np.asarray(w, dtype=np.float32).astype(np.float64))
     a1 = np.tanh(np.asarray(x, dtype=np.float32).astype(np.float64) @ W1.T + b1)
     a2 = np.tanh(bf16(a1) @ bf16(W2).T + b2)
-    return a2 @ W3 + b3[0]
+    return a2 @ W3.T + b3
 
 
-def drop_features(T_r, radius, kappa, k, nx, ny, cx=None, cy=None):
-    """Normalised features of every node (ny*nx, 5) of a drop of `radius`
-    centred at (cx, cy) (default the domain centre), plain distances."""
+def drop_geometry(radius, nx, ny, cx=None, cy=None):
+    """(r - R, theta) of every node (ny*nx,) of a drop of `radius` centred
+    at (cx, cy) (default the domain centre); plain distances."""
     cx = nx / 2.0 if cx is None else cx
     cy = ny / 2.0 if cy is None else cy
     y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
                        indexing="ij")
-    d = np.sqrt((x - cx) ** 2 + (y - cy) ** 2) - radius
-    f = np.empty((nx * ny, 5))
+    dx, dy = (x - cx).ravel(), (y - cy).ravel()
+    return np.sqrt(dx * dx + dy * dy) - radius, np.arctan2(dy, dx)
+
+
+def drop_features(T_r, radius, kappa, k, nx, ny, cx=None, cy=None):
+    """Normalised features (ny*nx, 7) of every node of a drop."""
+    d, th = drop_geometry(radius, nx, ny, cx, cy)
+    f = np.empty((nx * ny, N_IN))
     f[:, 0] = T_r
     f[:, 1] = radius / R_REF
     f[:, 2] = kappa
     f[:, 3] = k
-    f[:, 4] = d.ravel()
+    f[:, 4] = d
+    f[:, 5] = np.cos(4.0 * th)
+    f[:, 6] = np.sin(4.0 * th)
     return (f - FEATURE_CENTER) / FEATURE_SCALE
+
+
+def symmetric_outputs(w, x, bf16=True):
+    """Outputs made symmetric under the square's reflections about the drop's
+    centre, which map (cos 4 theta, sin 4 theta) to (cos 4 theta,
+    -sin 4 theta): with y+ at x and y- at x with its last feature negated,
+    (y0, y1) are the even parts and y2 the odd part."""
+    xm = np.array(x, dtype=np.float64)
+    xm[:, -1] = -xm[:, -1]
+    fwd = forward_bf16 if bf16 else (lambda w_, x_: forward(w_, x_)[0])
+    yp, ym = fwd(w, x), fwd(w, xm)
+    y = 0.5 * (yp + ym)
+    y[:, 2] = 0.5 * (yp[:, 2] - ym[:, 2])
+    return y
+
+
+def velocity_from_output(y, theta):
+    """(ux, uy) from the radial and azimuthal outputs (units of U_SCALE)."""
+    ur, ut = U_SCALE * y[:, 1], U_SCALE * y[:, 2]
+    c, s = np.cos(theta), np.sin(theta)
+    return ur * c - ut * s, ur * s + ut * c
+
+
+def drop_velocity(y, radius, nx, ny, cx=None, cy=None):
+    """Velocity field (ny, nx) x 2 of a drop from symmetric outputs: the polar
+    components rotated to (ux, uy), with the x (y) velocity zero on nodes
+    that are their own mirror image about x = cx (y = cy) in the periodic
+    mesh -- the centre column (row) and, for cx = nx/2 (cy = ny/2), the edge
+    column (row) -- as mirror symmetry demands."""
+    cx = nx / 2.0 if cx is None else cx
+    cy = ny / 2.0 if cy is None else cy
+    _, th = drop_geometry(radius, nx, ny, cx, cy)
+    ux, uy = velocity_from_output(y, th)
+    ux, uy = ux.reshape(ny, nx), uy.reshape(ny, nx)
+    xs, ys = np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64)
+    ux[:, np.fmod(2.0 * (xs - cx), nx) == 0.0] = 0.0
+    uy[np.fmod(2.0 * (ys - cy), ny) == 0.0, :] = 0.0
+    return ux, uy
 
 
 def density_from_output(y, rho_g, rho_l):

@@ -493,6 +493,30 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int src_on_device)
     return LBM_OK;
 }
 
+lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int src_on_device)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    const size_t N = c->N;
+    double *fx = c->obs, *ux = c->obs + N, *uy = c->obs + 2 * N;
+    const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if ((st = enqueue_fields(c)) != LBM_OK) return st;
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, nullptr, nullptr, nullptr,
+                                  fx, c->stream));
+    if (vx)
+        HIP_OR(c, hipMemcpyAsync(ux, vx, N * sizeof(double), kind, c->stream));
+    else
+        HIP_OR(c, hipMemsetAsync(ux, 0, N * sizeof(double), c->stream));
+    if (vy)
+        HIP_OR(c, hipMemcpyAsync(uy, vy, N * sizeof(double), kind, c->stream));
+    else
+        HIP_OR(c, hipMemsetAsync(uy, 0, N * sizeof(double), c->stream));
+    HIP_OR(c, launch_bare_velocity(c->kp, c->rho, fx, c->fy, ux, uy, c->stream));
+    HIP_OR(c, launch_init_feq(c->kp, c->rho, ux, uy, c->f[c->cur], c->stream));
+    HIP_OR(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
 {
     lbm_status st = enter(c);
@@ -1126,6 +1150,38 @@ lbm_status lbm_batch_get_state(lbm_batch *b, int32_t sim, double *f)
     BHIP_OR(b, hipMemcpyAsync(f, b->sb[sim].f[sim_parity(b, sim)], 9 * b->N[sim] * sizeof(double),
                               hipMemcpyDeviceToHost, b->stream));
     BHIP_OR(b, hipStreamSynchronize(b->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, const double *vy)
+{
+    lbm_status st = benter(b);
+    if (st != LBM_OK) return st;
+    if (sim < 0 || sim >= b->n) return bfail(b, LBM_E_INVALID, "no such simulation");
+    const KParams &k = b->kp[sim];
+    const SimBuffers &q = b->sb[sim];
+    const size_t N = b->N[sim];
+    double *tmp = nullptr;
+    BHIP_OR(b, hipStreamSynchronize(b->stream));
+    BHIP_OR(b, hipMalloc(&tmp, 3 * N * sizeof(double)));
+    double *fx = tmp, *ux = tmp + N, *uy = tmp + 2 * N;
+    double *fc = q.f[sim_parity(b, sim)];
+    hipError_t e = launch_rows_rho(k, fc, q.rho, q.dxx, b->stream);
+    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.dxx, q.mu, q.fy, b->stream);
+    if (e == hipSuccess)
+        e = launch_rows_observe(k, fc, q.mu, q.fy, nullptr, nullptr, nullptr, fx, b->stream);
+    if (e == hipSuccess)
+        e = vx ? hipMemcpyAsync(ux, vx, N * sizeof(double), hipMemcpyHostToDevice, b->stream)
+               : hipMemsetAsync(ux, 0, N * sizeof(double), b->stream);
+    if (e == hipSuccess)
+        e = vy ? hipMemcpyAsync(uy, vy, N * sizeof(double), hipMemcpyHostToDevice, b->stream)
+               : hipMemsetAsync(uy, 0, N * sizeof(double), b->stream);
+    if (e == hipSuccess) e = launch_bare_velocity(k, q.rho, fx, q.fy, ux, uy, b->stream);
+    if (e == hipSuccess) e = launch_init_feq(k, q.rho, ux, uy, fc, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess)
+        return bfail(b, LBM_E_DEVICE, std::string("set_velocity: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 

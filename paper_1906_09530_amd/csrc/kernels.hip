@@ -506,6 +506,30 @@ hipError_t launch_rows_observe(const KParams &p, const double *f, const double *
     return hipGetLastError();
 }
 
+// u = v - F / (2 rho): the bare velocity whose equilibrium carries the fluid
+// velocity v under the force F (Sec. 2, the half-force shift of Eq. 5).
+__global__ void k_bare_velocity(size_t N, const double *__restrict__ rho,
+                                const double *__restrict__ fx, const double *__restrict__ fy,
+                                double *__restrict__ ux, double *__restrict__ uy)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < N;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double h = 0.5 / rho[i];
+        ux[i] -= h * fx[i];
+        uy[i] -= h * fy[i];
+    }
+}
+
+hipError_t launch_bare_velocity(const KParams &p, const double *rho, const double *fx,
+                                const double *fy, double *ux, double *uy, hipStream_t s)
+{
+    const size_t N = (size_t)p.nx * p.ny;
+    int blocks = (int)((N + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_bare_velocity, dim3(blocks), dim3(256), 0, s, N, rho, fx, fy, ux, uy);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_feq(const KParams &p, const double *rho0, const double *ux0,
                            const double *uy0, double *f, hipStream_t s)
 {

@@ -57,6 +57,9 @@ hipError_t launch_rows_observe(const KParams &p, const double *f, const double *
 // f = feq(rho0, u0) (u0 pointers may be null: rest).
 hipError_t launch_init_feq(const KParams &p, const double *rho0, const double *ux0,
                            const double *uy0, double *f, hipStream_t s);
+// In place: (ux, uy) <- (ux, uy) - (fx, fy) / (2 rho).
+hipError_t launch_bare_velocity(const KParams &p, const double *rho, const double *fx,
+                                const double *fy, double *ux, double *uy, hipStream_t s);
 // rho of f compared with prev: per-block max |rho - prev| and a non-finite
 // flag into partial[2*block]; prev <- rho.  Then one block folds the partials
 // into out[0] (max) and out[1] (flag).

@@ -1,10 +1,12 @@
-// Kernels of the learned warm start: a 5-128-128-1 tanh network trained in
+// Kernels of the learned warm start: a 7-128-128-3 tanh network trained in
 // FP32 (forward, backpropagation, Adam) and evaluated in BF16 on the matrix
-// cores, and the warm-start density field of a static drop built from it.
+// cores, and the warm-start density and velocity fields of a static drop
+// built from it.
 //
-// Parameters (FP32, one flat array): W1 [128][5], b1 [128], W2 [128][128],
-// b2 [128], W3 [128], b3 [1].  Network: a1 = tanh(W1 x + b1),
-// a2 = tanh(W2 a1 + b2), y = W3 . a2 + b3; loss = mean (y - t)^2.
+// Parameters (FP32, one flat array): W1 [128][7], b1 [128], W2 [128][128],
+// b2 [128], W3 [3][128], b3 [3].  Network: a1 = tanh(W1 x + b1),
+// a2 = tanh(W2 a1 + b2), y = W3 a2 + b3; loss = mean over samples of
+// sum_j (y_j - t_j)^2.
 #include "mlp.hpp"
 
 namespace cplbm {
@@ -12,10 +14,10 @@ namespace mlp {
 
 namespace {
 
-constexpr int H = kHidden, NI = kInputs;
+constexpr int H = kHidden, NI = kInputs, NO = kOutputs;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * NI, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
-              OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + H;
-static_assert(OFF_B3 + 1 == kParams, "parameter layout");
+              OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + NO * H;
+static_assert(OFF_B3 + NO == kParams, "parameter layout");
 
 // ---- FP32 forward (and the first backward step) --------------------------
 // A block holds 32 samples; thread t works on sample t / 8 and hidden units
@@ -97,27 +99,43 @@ __global__ __launch_bounds__(FT) void k_forward_f32(const float *__restrict__ w,
             }
         }
     }
-    // layer 3: partial dot over this thread's units, then over the 8 threads
-    float a2v[FU], part = 0.f;
+    // layer 3: partial dots over this thread's units, then over the 8 threads
+    float a2v[FU], y[NO];
 #pragma unroll
-    for (int j = 0; j < FU; ++j) {
-        a2v[j] = tanhf(z2[j]);
-        part = fmaf(w[OFF_W3 + u0 + j], a2v[j], part);
+    for (int j = 0; j < FU; ++j) a2v[j] = tanhf(z2[j]);
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        float part = 0.f;
+#pragma unroll
+        for (int j = 0; j < FU; ++j) part = fmaf(w[OFF_W3 + o * H + u0 + j], a2v[j], part);
+        part += __shfl_xor(part, 1);
+        part += __shfl_xor(part, 2);
+        part += __shfl_xor(part, 4);
+        y[o] = part + w[OFF_B3 + o];
     }
-    part += __shfl_xor(part, 1);
-    part += __shfl_xor(part, 2);
-    part += __shfl_xor(part, 4);
-    const float y = part + w[OFF_B3];
     if (!TRAIN) {
-        if (ok && (tid % 8) == 0) y_out[s] = y;
+        if (ok && (tid % 8) == 0) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) y_out[(size_t)s * NO + o] = y[o];
+        }
         return;
     }
-    const float err = ok ? y - t[src] : 0.f;
-    const float dy = 2.f * err * inv_n;
+    float dy[NO], sq = 0.f;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        const float err = ok ? y[o] - t[(size_t)src * NO + o] : 0.f;
+        sq = fmaf(err, err, sq);
+        dy[o] = 2.f * err * inv_n;
+    }
     if (ok) {
         float d[FU];
 #pragma unroll
-        for (int j = 0; j < FU; ++j) d[j] = dy * w[OFF_W3 + u0 + j] * (1.f - a2v[j] * a2v[j]);
+        for (int j = 0; j < FU; ++j) {
+            float back = 0.f;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) back = fmaf(dy[o], w[OFF_W3 + o * H + u0 + j], back);
+            d[j] = back * (1.f - a2v[j] * a2v[j]);
+        }
 #pragma unroll
         for (int j = 0; j < FU; j += 4) {
             *reinterpret_cast<float4 *>(a2g + (size_t)s * H + u0 + j) =
@@ -125,10 +143,13 @@ __global__ __launch_bounds__(FT) void k_forward_f32(const float *__restrict__ w,
             *reinterpret_cast<float4 *>(dz2g + (size_t)s * H + u0 + j) =
                 make_float4(d[j], d[j + 1], d[j + 2], d[j + 3]);
         }
-        if ((tid % 8) == 0) dyg[s] = dy;
+        if ((tid % 8) == 0) {
+#pragma unroll
+            for (int o = 0; o < NO; ++o) dyg[(size_t)s * NO + o] = dy[o];
+        }
     }
     // block sum of squared errors (fixed order), one partial per block
-    if ((tid % 8) == 0) red[sl] = err * err;
+    if ((tid % 8) == 0) red[sl] = sq;
     __syncthreads();
     if (tid == 0) {
         float acc = 0.f;
@@ -277,11 +298,11 @@ __device__ __forceinline__ void bf16_tile_load_w2(const float *__restrict__ w, B
     for (int e = threadIdx.x; e < H * H; e += IT) t.w2[e] = to_bf16(w[OFF_W2 + e]);
 }
 
-// x: this thread's features (sample threadIdx.x / 4 of the tile); returns y
-// of sample 16 (threadIdx.x / 64) + 4 ((threadIdx.x % 64) / 16) + r in ys[r]
-// (valid in lanes with (lane % 16) == 0 after the reduction; all lanes hold it).
+// x: this thread's features (sample threadIdx.x / 4 of the tile); returns the
+// outputs of sample 16 (threadIdx.x / 64) + 4 ((threadIdx.x % 64) / 16) + r in
+// ys[o][r] (every lane of a 16-lane group holds them after the reduction).
 __device__ __forceinline__ void bf16_tile_eval(const float *__restrict__ w, BfTile &t,
-                                               const float (&xv)[NI], float (&ys)[4])
+                                               const float (&xv)[NI], float (&ys)[NO][4])
 {
     const int tid = threadIdx.x;
     const int sl = tid / 4, u0 = (tid % 4) * 32;
@@ -295,7 +316,7 @@ __device__ __forceinline__ void bf16_tile_eval(const float *__restrict__ w, BfTi
     __syncthreads();
     const int wave = tid / 64, lane = tid % 64;
     const int row = lane % 16, kq = 4 * (lane / 16);
-    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    float part[NO][4] = {};
     for (int nt = 0; nt < H / 16; ++nt) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -306,18 +327,25 @@ __device__ __forceinline__ void bf16_tile_eval(const float *__restrict__ w, BfTi
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
         }
         const int u = nt * 16 + row;  // output unit of this lane
-        const float bu = w[OFF_B2 + u], w3 = w[OFF_W3 + u];
+        const float bu = w[OFF_B2 + u];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) part[r] = fmaf(w3, tanhf(acc[r] + bu), part[r]);
+        for (int r = 0; r < 4; ++r) {
+            const float a2 = tanhf(acc[r] + bu);
+#pragma unroll
+            for (int o = 0; o < NO; ++o) part[o][r] = fmaf(w[OFF_W3 + o * H + u], a2, part[o][r]);
+        }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float p = part[r];
-        p += __shfl_xor(p, 1);
-        p += __shfl_xor(p, 2);
-        p += __shfl_xor(p, 4);
-        p += __shfl_xor(p, 8);
-        ys[r] = p + w[OFF_B3];
+    for (int o = 0; o < NO; ++o) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float p = part[o][r];
+            p += __shfl_xor(p, 1);
+            p += __shfl_xor(p, 2);
+            p += __shfl_xor(p, 4);
+            p += __shfl_xor(p, 8);
+            ys[o][r] = p + w[OFF_B3 + o];
+        }
     }
 }
 
@@ -331,65 +359,104 @@ __global__ __launch_bounds__(IT) void k_infer_bf16(const float *__restrict__ w,
     float xv[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) xv[i] = s < n ? x[(size_t)s * NI + i] : 0.f;
-    float ys[4];
+    float ys[NO][4];
     bf16_tile_eval(w, t, xv, ys);
     const int lane = threadIdx.x % 64;
     if (lane % 16 == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int so = blockIdx.x * IS + (threadIdx.x / 64) * 16 + 4 * (lane / 16) + r;
-            if (so < n) y[so] = ys[r];
+            if (so < n) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) y[(size_t)so * NO + o] = ys[o][r];
+            }
         }
     }
 }
 
-// ---- warm-start density field of a static drop ----------------------------
-// Node n = y * nx + x has features (T/Tc, R / 256, kappa, k, r - R),
-// normalised by (f - centre) / scale; the network's output is the normalised
-// log density, rho = exp(ln rho_g + y (ln rho_l - ln rho_g)).  Each block
-// writes rho for its 64 nodes and the partial sums of rho and of the
-// mass-matching weight max((rho - rho_g)(rho_l - rho), 0).
-__global__ __launch_bounds__(IT) void k_ws_field(const float *__restrict__ w, WsDrop d,
-                                                 double *__restrict__ rho,
-                                                 double *__restrict__ part)
+// ---- warm-start fields of a static drop ------------------------------------
+// Node n = y * nx + x, at distance r and polar angle theta from the centre,
+// has features (T/Tc, R / R_ref, kappa, k, r - R, cos 4 theta, sin 4 theta),
+// normalised by (f - centre) / scale.
+__device__ __forceinline__ void node_polar(const WsDrop &d, int n, double &r, double &c,
+                                           double &sn)
 {
-    __shared__ BfTile t;
-    __shared__ double red[2][IS];
-    bf16_tile_load_w2(w, t);
+    const int yy = n / d.nx, xx = n - yy * d.nx;
+    const double dx = xx - d.cx, dy = yy - d.cy;
+    r = sqrt(dx * dx + dy * dy);
+    c = r > 0.0 ? dx / r : 1.0;  // theta = 0 at the centre itself
+    sn = r > 0.0 ? dy / r : 0.0;
+}
+
+// Rows n and N + n of x: the features of node n, and those of its mirror
+// image (sin 4 theta negated; every reflection of the square maps
+// (cos 4 theta, sin 4 theta) to (cos 4 theta, -sin 4 theta)).
+__global__ void k_ws_features(WsDrop d, float *__restrict__ x)
+{
     const int N = d.nx * d.ny;
-    const int s = blockIdx.x * IS + threadIdx.x / 4;
-    float xv[NI];
-    {
-        const int sc = s < N ? s : N - 1;
-        const int yy = sc / d.nx, xx = sc - yy * d.nx;
-        const double dx = xx - d.cx, dy = yy - d.cy;
-        const double r = sqrt(dx * dx + dy * dy) - d.radius;
-        const double f[NI] = {d.T_r, d.radius / d.radius_ref, d.kappa, d.k, r};
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double r, c, sn;
+    node_polar(d, n, r, c, sn);
+    const double c2 = c * c - sn * sn, s2 = 2.0 * c * sn;
+    const double f[NI] = {d.T_r, d.radius / d.radius_ref, d.kappa, d.k, r - d.radius,
+                          c2 * c2 - s2 * s2, 2.0 * s2 * c2};
 #pragma unroll
-        for (int i = 0; i < NI; ++i) xv[i] = (float)((f[i] - d.center[i]) / d.scale[i]);
+    for (int i = 0; i < NI; ++i) {
+        const double v = (f[i] - d.center[i]) / d.scale[i];
+        x[(size_t)n * NI + i] = (float)v;
+        x[((size_t)N + n) * NI + i] = (float)(i == NI - 1 ? -v : v);
     }
-    float ys[4];
-    bf16_tile_eval(w, t, xv, ys);
-    const int lane = threadIdx.x % 64;
-    if (lane % 16 == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int sl = (threadIdx.x / 64) * 16 + 4 * (lane / 16) + r;
-            const int so = blockIdx.x * IS + sl;
-            double rv = 0.0, wv = 0.0;
-            if (so < N) {
-                rv = exp(d.ln_rho_g + (double)ys[r] * (d.ln_rho_l - d.ln_rho_g));
-                rho[so] = rv;
-                wv = fmax((rv - d.rho_g) * (d.rho_l - rv), 0.0);
-            }
-            red[0][sl] = rv;
-            red[1][sl] = wv;
+}
+
+// Outputs to fields, made exactly symmetric under the reflections of the
+// square about the drop's centre: with y+ the outputs of node n and y- those
+// of its mirror features, y0 = (y0+ + y0-)/2 and the radial velocity
+// (y1+ + y1-)/2 are even, the azimuthal velocity (y2+ - y2-)/2 odd, and the
+// velocity normal to a mirror line vanishes on it, so the proposed state
+// carries no net momentum and the drop does not drift.  rho = exp(ln rho_g + y0 (ln rho_l
+// - ln rho_g)); velocity in units of u_scale.  Each block of 256 nodes also
+// writes the partial sums of rho and of the mass-matching weight
+// max((rho - rho_g)(rho_l - rho), 0).
+constexpr int MT = 256;
+
+__global__ __launch_bounds__(MT) void k_ws_map(WsDrop d, const float *__restrict__ y,
+                                               double *__restrict__ rho,
+                                               double *__restrict__ ux,
+                                               double *__restrict__ uy,
+                                               double *__restrict__ part)
+{
+    __shared__ double red[2][MT];
+    const int N = d.nx * d.ny;
+    const int n = blockIdx.x * MT + threadIdx.x;
+    double rv = 0.0, wv = 0.0;
+    if (n < N) {
+        const float *yp = y + (size_t)n * NO, *ym = y + ((size_t)N + n) * NO;
+        const double y0 = 0.5 * ((double)yp[0] + (double)ym[0]);
+        rv = exp(d.ln_rho_g + y0 * (d.ln_rho_l - d.ln_rho_g));
+        rho[n] = rv;
+        wv = fmax((rv - d.rho_g) * (d.rho_l - rv), 0.0);
+        if (ux) {
+            double r, c, sn;
+            node_polar(d, n, r, c, sn);
+            const double ur = d.u_scale * 0.5 * ((double)yp[1] + (double)ym[1]);
+            const double ut = d.u_scale * 0.5 * ((double)yp[2] - (double)ym[2]);
+            // a node that is its own mirror image about the line x = cx (the
+            // centre column, and the edge column of a periodic mesh when cx
+            // sits half a period away) has no x velocity; likewise in y
+            const int yy = n / d.nx, xx = n - yy * d.nx;
+            const bool self_x = fmod(2.0 * (xx - d.cx), (double)d.nx) == 0.0;
+            const bool self_y = fmod(2.0 * (yy - d.cy), (double)d.ny) == 0.0;
+            ux[n] = self_x ? 0.0 : ur * c - ut * sn;
+            uy[n] = self_y ? 0.0 : ur * sn + ut * c;
         }
     }
+    red[0][threadIdx.x] = rv;
+    red[1][threadIdx.x] = wv;
     __syncthreads();
     if (threadIdx.x < 2) {
         double acc = 0.0;
-        for (int i = 0; i < IS; ++i) acc += red[threadIdx.x][i];
+        for (int i = 0; i < MT; ++i) acc += red[threadIdx.x][i];
         part[2 * blockIdx.x + threadIdx.x] = acc;
     }
 }
@@ -407,13 +474,16 @@ __global__ void k_ws_fold(const double *__restrict__ part, int nb, double target
     c[0] = sw > 0.0 ? (target - sr) / sw : 0.0;
 }
 
+// rho += c w; a density that ends non-positive or non-finite sets *bad.
 __global__ void k_ws_apply(double *__restrict__ rho, int N, double rho_g, double rho_l,
-                           const double *__restrict__ c)
+                           const double *__restrict__ c, int *__restrict__ bad)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     const double r = rho[i];
-    rho[i] = r + c[0] * fmax((r - rho_g) * (rho_l - r), 0.0);
+    const double v = r + c[0] * fmax((r - rho_g) * (rho_l - r), 0.0);
+    rho[i] = v;
+    if (!(v > 0.0 && v < INFINITY)) *bad = 1;
 }
 
 }  // namespace
@@ -434,7 +504,7 @@ static TrainWs train_ws_layout(int batch)
     L.dz2 = L.a2 + up(B * H);
     L.dz1 = L.dz2 + up(B * H);
     L.dy = L.dz1 + up(B * H);
-    L.lp = L.dy + up(B);
+    L.lp = L.dy + up(B * NO);
     L.total = L.lp + up((B + FS - 1) / FS);
     return L;
 }
@@ -462,8 +532,8 @@ hipError_t train_step(float *w, float *g, float *m, float *v, const float *x, co
     atb(dz1, H, H, nullptr, 0, 1, g + OFF_B1);   // db1
     atb(dz2, H, H, a1, H, H, g + OFF_W2);        // dW2[u][k] = sum dz2[s][u] a1[s][k]
     atb(dz2, H, H, nullptr, 0, 1, g + OFF_B2);   // db2
-    atb(dy, 1, 1, a2, H, H, g + OFF_W3);         // dW3[u] = sum dy[s] a2[s][u]
-    atb(dy, 1, 1, nullptr, 0, 1, g + OFF_B3);    // db3
+    atb(dy, NO, NO, a2, H, H, g + OFF_W3);       // dW3[o][u] = sum dy[s][o] a2[s][u]
+    atb(dy, NO, NO, nullptr, 0, 1, g + OFF_B3);  // db3
     if (loss_dev)
         hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, s, lp, nb, 1.f / batch, loss_dev);
     if (m)
@@ -488,17 +558,21 @@ hipError_t forward_bf16(const float *w, const float *x, int n, float *y, hipStre
     return hipGetLastError();
 }
 
-int ws_field_blocks(int nodes) { return (nodes + IS - 1) / IS; }
+int ws_field_blocks(int nodes) { return (nodes + MT - 1) / MT; }
 
-hipError_t warm_start_field(const float *w, const WsDrop &d, double target_mass, double *rho,
-                            double *part, double *c, hipStream_t s)
+hipError_t warm_start_field(const float *w, const WsDrop &d, bool bf16, double target_mass,
+                            float *x, float *y, double *rho, double *ux, double *uy,
+                            double *part, double *c, int *bad, hipStream_t s)
 {
     const int N = d.nx * d.ny;
     const int nb = ws_field_blocks(N);
-    hipLaunchKernelGGL(k_ws_field, dim3(nb), dim3(IT), 0, s, w, d, rho, part);
+    hipLaunchKernelGGL(k_ws_features, dim3(nb), dim3(MT), 0, s, d, x);
+    hipError_t e = bf16 ? forward_bf16(w, x, 2 * N, y, s) : forward_f32(w, x, 2 * N, y, bad, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ws_map, dim3(nb), dim3(MT), 0, s, d, y, rho, ux, uy, part);
     hipLaunchKernelGGL(k_ws_fold, dim3(1), dim3(64), 0, s, part, nb, target_mass, c);
     hipLaunchKernelGGL(k_ws_apply, dim3((N + 255) / 256), dim3(256), 0, s, rho, N, d.rho_g,
-                       d.rho_l, c);
+                       d.rho_l, c, bad);
     return hipGetLastError();
 }
 

@@ -9,8 +9,9 @@
 namespace cplbm {
 namespace mlp {
 
-constexpr int kInputs = 5, kHidden = 128;
-constexpr int kParams = kHidden * kInputs + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
+constexpr int kInputs = 7, kHidden = 128, kOutputs = 3;
+constexpr int kParams = kHidden * kInputs + kHidden + kHidden * kHidden + kHidden +
+                        kOutputs * kHidden + kOutputs;
 
 // A static drop whose initial density the network proposes.
 struct WsDrop {
@@ -18,6 +19,7 @@ struct WsDrop {
     double cx, cy, radius, T_r, kappa, k;
     double rho_g, rho_l, ln_rho_g, ln_rho_l;  // Maxwell pair of the drop's EOS and T
     double radius_ref;                        // feature 2 is radius / radius_ref
+    double u_scale;                           // velocity outputs are in units of u_scale
     double center[kInputs], scale[kInputs];   // x_i = (f_i - center_i) / scale_i
 };
 
@@ -33,14 +35,21 @@ hipError_t train_step(float *w, float *g, float *m, float *v, const float *x, co
                       int nsrc, const int32_t *idx, int batch, float lr, float b1, float b2,
                       float eps, float c1, float c2, float *ws, int *bad, float *loss_dev,
                       hipStream_t s);
-// y[n] of x[n][5]: FP32 throughout, or the hidden product in BF16 (matrix cores).
+// y[n][3] of x[n][7]: FP32 throughout, or the hidden product in BF16 (matrix cores).
 hipError_t forward_f32(const float *w, const float *x, int n, float *y, int *bad, hipStream_t s);
 hipError_t forward_bf16(const float *w, const float *x, int n, float *y, hipStream_t s);
-// Warm-start density (FP64, ny*nx) of drop d, mass matched to target_mass:
-// part holds 2 * ws_field_blocks(nx*ny) doubles, c one double.
+// Warm-start fields of drop d: features of every node and of its mirror
+// image into x (2*nx*ny*7 floats), network outputs into y (2*nx*ny*3 floats;
+// BF16 matrix-core or FP32 inference), then rho (FP64, ny*nx) mass matched
+// to target_mass and the fluid velocity (ux, uy, both null or both not),
+// symmetric under the square's reflections.  part holds
+// 2 * ws_field_blocks(nx*ny) doubles; c receives the mass-matching
+// coefficient; *bad is set when a matched density is not positive and
+// finite.
 int ws_field_blocks(int nodes);
-hipError_t warm_start_field(const float *w, const WsDrop &d, double target_mass, double *rho,
-                            double *part, double *c, hipStream_t s);
+hipError_t warm_start_field(const float *w, const WsDrop &d, bool bf16, double target_mass,
+                            float *x, float *y, double *rho, double *ux, double *uy,
+                            double *part, double *c, int *bad, hipStream_t s);
 
 }  // namespace mlp
 }  // namespace cplbm

@@ -23,6 +23,8 @@ struct lbm_mlp {
     size_t ws_floats = 0;
     double *field = nullptr;  // warm-start partial sums and the correction
     size_t field_doubles = 0;
+    float *fxy = nullptr;  // warm-start features and outputs
+    size_t fxy_floats = 0;
     int64_t steps = 0;
     std::string err;
 };
@@ -208,12 +210,15 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t nsa
 int64_t lbm_mlp_steps(const lbm_mlp *m) { return m ? m->steps : -1; }
 
 lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, double cy,
-                               double radius, double target_mass, double *rho)
+                               double radius, double target_mass, int bf16, double *rho,
+                               double *ux, double *uy)
 {
     lbm_status st = menter(m);
     if (st != LBM_OK) return st;
     if (!p || !rho) return mfail(m, LBM_E_INVALID, "params or rho is NULL");
-    if (p->nx < 1 || p->ny < 1 || (int64_t)p->nx * p->ny > INT32_MAX / 2)
+    if ((ux == nullptr) != (uy == nullptr))
+        return mfail(m, LBM_E_INVALID, "ux and uy must both be given or both be NULL");
+    if (p->nx < 1 || p->ny < 1 || (int64_t)p->nx * p->ny > (1 << 25))
         return mfail(m, LBM_E_INVALID, "bad mesh size");
     if (!(std::isfinite(cx) && std::isfinite(cy) && radius > 0 && std::isfinite(radius) &&
           target_mass > 0 && std::isfinite(target_mass)))
@@ -235,22 +240,38 @@ lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, doubl
     d.ln_rho_g = std::log(g);
     d.ln_rho_l = std::log(l);
     d.radius_ref = 256.0;
-    const double center[5] = {0.5, 0.25, 0.1, 0.25, 0.0}, scale[5] = {0.25, 0.1, 0.1, 0.1, 8.0};
-    for (int i = 0; i < 5; ++i) {
+    d.u_scale = 1e-3;
+    const double center[mlp::kInputs] = {0.5, 0.25, 0.1, 0.25, 0.0, 0.0, 0.0};
+    const double scale[mlp::kInputs] = {0.25, 0.1, 0.1, 0.1, 8.0, 1.0, 1.0};
+    for (int i = 0; i < mlp::kInputs; ++i) {
         d.center[i] = center[i];
         d.scale[i] = scale[i];
     }
-    const size_t need = 2 * (size_t)mlp::ws_field_blocks(d.nx * d.ny) + 1;
-    if (need > m->field_doubles) {
+    const size_t N = (size_t)d.nx * d.ny;
+    const size_t need = 2 * (size_t)mlp::ws_field_blocks((int)N) + 1;
+    const size_t need_f = 2 * N * (mlp::kInputs + mlp::kOutputs);
+    if (need > m->field_doubles || need_f > m->fxy_floats) {
         MHIP_OR(m, hipStreamSynchronize(m->stream));
         if (m->field) MHIP_OR(m, hipFree(m->field));
+        if (m->fxy) MHIP_OR(m, hipFree(m->fxy));
         m->field = nullptr;
-        m->field_doubles = 0;
+        m->fxy = nullptr;
+        m->field_doubles = m->fxy_floats = 0;
         MHIP_OR(m, hipMalloc(&m->field, need * sizeof(double)));
+        MHIP_OR(m, hipMalloc(&m->fxy, need_f * sizeof(float)));
         m->field_doubles = need;
+        m->fxy_floats = need_f;
     }
-    MHIP_OR(m, mlp::warm_start_field(m->w, d, target_mass, rho, m->field + 1, m->field,
-                                     m->stream));
+    float *x = m->fxy, *y = m->fxy + 2 * N * mlp::kInputs;
+    MHIP_OR(m, hipMemsetAsync(m->bad, 0, sizeof(int), m->stream));
+    MHIP_OR(m, mlp::warm_start_field(m->w, d, bf16 != 0, target_mass, x, y, rho, ux, uy,
+                                     m->field + 1, m->field, m->bad, m->stream));
+    int bad = 0;
+    MHIP_OR(m, hipMemcpyAsync(&bad, m->bad, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+    MHIP_OR(m, hipStreamSynchronize(m->stream));
+    if (bad)
+        return mfail(m, LBM_E_DOMAIN,
+                     "the proposed density is too far from the target mass to match it");
     return LBM_OK;
 }
 
@@ -259,7 +280,7 @@ void lbm_mlp_destroy(lbm_mlp *m)
     if (!m) return;
     (void)hipSetDevice(m->device);
     (void)hipStreamSynchronize(m->stream);
-    void *ptrs[] = {m->w, m->g, m->m, m->v, m->loss, m->bad, m->ws, m->field};
+    void *ptrs[] = {m->w, m->g, m->m, m->v, m->loss, m->bad, m->ws, m->field, m->fxy};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete m;

@@ -130,11 +130,12 @@ def warmstart_members(seed, count, *, t_lo, t_hi, r_lo, r_hi, k_lo, k_hi):
              "k": k_lo + (k_hi - k_lo) * float(c)} for a, b, c in u]
 
 
-def network_init(seed, n_in=5, n_hid=128):
-    """Initial parameters of the n_in-n_hid-n_hid-1 network in the flat order
-    W1, b1, W2, b2, W3, b3: weights uniform in +-sqrt(6 / (fan_in + fan_out))
-    (Glorot and Bengio, 2010), biases zero; float32."""
-    shapes = [(n_hid, n_in), (n_hid,), (n_hid, n_hid), (n_hid,), (1, n_hid), (1,)]
+def network_init(seed, n_in=7, n_hid=128, n_out=3):
+    """Initial parameters of the n_in-n_hid-n_hid-n_out network in the flat
+    order W1, b1, W2, b2, W3, b3: weights uniform in
+    +-sqrt(6 / (fan_in + fan_out)) (Glorot and Bengio, 2010), biases zero;
+    float32."""
+    shapes = [(n_hid, n_in), (n_hid,), (n_hid, n_hid), (n_hid,), (n_out, n_hid), (n_out,)]
     total = sum(int(np.prod(s)) for s in shapes)
     u = 2.0 * uniform01(seed, total) - 1.0
     out, o = [], 0

@@ -106,7 +106,9 @@ def load():
         "lbm_mlp_train": (i32, [P, P, P, i64, P, i64, i64, C.c_float, C.c_float, C.c_float,
                                 C.c_float, P]),
         "lbm_mlp_steps": (i64, [P]),
-        "lbm_warm_start_drop": (i32, [P, pp, d, d, d, d, P]),
+        "lbm_warm_start_drop": (i32, [P, pp, d, d, d, d, i32, P, P, P]),
+        "lbm_set_velocity": (i32, [P, P, P, i32]),
+        "lbm_batch_set_velocity": (i32, [P, i32, P, P]),
         "lbm_mlp_destroy": (None, [P]),
         "lbm_mlp_last_error": (C.c_char_p, [P]),
     }
@@ -254,6 +256,15 @@ class Solver:
         _check(load().lbm_get_state(self.ctx, _ptr(f), int(device)), self.ctx)
         return f
 
+    def set_velocity(self, vx=None, vy=None):
+        """Fluid velocity v = u + F/(2 rho) of the current density (None: rest)."""
+        dev = _is_device(vx) or _is_device(vy)
+        if not dev:
+            vx = None if vx is None else np.ascontiguousarray(vx, dtype=np.float64)
+            vy = None if vy is None else np.ascontiguousarray(vy, dtype=np.float64)
+        self._vkeep = (vx, vy)
+        _check(load().lbm_set_velocity(self.ctx, _ptr(vx), _ptr(vy), int(dev)), self.ctx)
+
     def set_state(self, f):
         dev = _is_device(f)
         if not dev:
@@ -332,6 +343,12 @@ class Batch:
     def steps_taken(self, sim):
         return load().lbm_batch_steps(self.b, int(sim))
 
+    def set_velocity(self, sim, vx=None, vy=None):
+        """Fluid velocity of simulation sim (host arrays; None: rest)."""
+        vx = None if vx is None else np.ascontiguousarray(vx, dtype=np.float64)
+        vy = None if vy is None else np.ascontiguousarray(vy, dtype=np.float64)
+        _bcheck(load().lbm_batch_set_velocity(self.b, int(sim), _ptr(vx), _ptr(vy)), self.b)
+
     def moments(self, sim):
         p = self.plist[sim]
         r, vx, vy = (np.empty((p.ny, p.nx)) for _ in range(3))
@@ -346,7 +363,8 @@ class Batch:
         return f
 
 
-MLP_PARAMS = 17409
+MLP_PARAMS = 17923
+MLP_INPUTS, MLP_OUTPUTS = 7, 3
 
 
 def _mcheck(st, m=None, ok=(LBM_OK,)):
@@ -396,9 +414,10 @@ class MLP:
         _mcheck(load().lbm_mlp_set_params(self.m, params.ctypes.data), self.m)
 
     def forward(self, x, bf16=False):
+        """(n, 3) outputs of samples x (n, 7), device tensors."""
         import torch
         n = x.shape[0]
-        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        y = torch.empty((n, MLP_OUTPUTS), dtype=torch.float32, device=x.device)
         _mcheck(load().lbm_mlp_forward(self.m, _dev_ptr(x, torch.float32), n,
                                        _dev_ptr(y, torch.float32), int(bool(bf16))), self.m)
         return y
@@ -428,11 +447,13 @@ class MLP:
     def steps(self):
         return load().lbm_mlp_steps(self.m)
 
-    def warm_start_drop(self, p, radius, target_mass, center=None):
-        """Warm-start density (device tensor (ny, nx), float64) of a drop."""
+    def warm_start_drop(self, p, radius, target_mass, center=None, bf16=True):
+        """Warm-start (rho, vx, vy) of a drop: device tensors (ny, nx), float64
+        (v is the fluid velocity, for set_velocity)."""
         import torch
         cx, cy = (p.nx / 2.0, p.ny / 2.0) if center is None else center
-        rho = torch.empty((p.ny, p.nx), dtype=torch.float64, device="cuda")
+        out = [torch.empty((p.ny, p.nx), dtype=torch.float64, device="cuda") for _ in range(3)]
         _mcheck(load().lbm_warm_start_drop(self.m, C.byref(p), cx, cy, radius, target_mass,
-                                           _dev_ptr(rho, torch.float64)), self.m)
-        return rho
+                                           int(bool(bf16)),
+                                           *[_dev_ptr(a, torch.float64) for a in out]), self.m)
+        return tuple(out)

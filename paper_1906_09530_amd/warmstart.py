@@ -1,13 +1,14 @@
 """Learned warm start of static drops (orchestration over the C ABI).
 
-The solver converges drops from the tanh start of Eq. 41 (Sec. 5.3); the
-converged profiles become training samples of the network of
+The solver converges drops from the tanh start of Eq. 41 (Sec. 5.3, zero
+velocity); the converged states become training samples of the network of
 include/lbm_warmstart.h, which the library trains with its own FP32 kernels;
-the trained network then proposes the initial density of new drops (BF16
-inference, mass matched to the tanh start), and both starts are run to the
-same convergence criterion.  Every numerical step (solver, training,
-inference, warm-start field) runs in the library's kernels; this module only
-draws the workload, assembles the samples and keeps the books.
+the trained network then proposes the initial density and velocity of new
+drops (BF16 inference, density mass matched to the tanh start), and both
+starts are run to the same convergence criterion.  Every numerical step
+(solver, training, inference, warm-start fields) runs in the library's
+kernels; this module only draws the workload, assembles the samples and
+keeps the books.
 
 Workload: Carnahan-Starling drops (a = 1, b = 4, R = 1) in square periodic
 meshes, kappa = 0.1, tau = 1, T/Tc, radius fraction and k drawn per drop.
@@ -19,9 +20,10 @@ import numpy as np
 from . import inputs, lbm
 
 KAPPA, TAU, WIDTH = 0.1, 1.0, 5.0
-FEATURE_CENTER = np.array([0.5, 0.25, 0.1, 0.25, 0.0])
-FEATURE_SCALE = np.array([0.25, 0.1, 0.1, 0.1, 8.0])
+FEATURE_CENTER = np.array([0.5, 0.25, 0.1, 0.25, 0.0, 0.0, 0.0])
+FEATURE_SCALE = np.array([0.25, 0.1, 0.1, 0.1, 8.0, 1.0, 1.0])
 R_REF = 256.0
+U_SCALE = 1e-3
 RANGES = dict(t_lo=0.35, t_hi=0.6, r_lo=0.15, r_hi=0.35, k_lo=0.15, k_hi=0.3)
 
 
@@ -34,12 +36,22 @@ def tanh_start(p, radius):
     return inputs.droplet(p.nx, p.ny, g, l, radius, WIDTH)[0]
 
 
-def converge(plist, rho0s, tol, every, max_steps, log=None):
+def _host(a):
+    if a is None:
+        return None
+    return a.cpu().numpy() if hasattr(a, "cpu") else a
+
+
+def converge(plist, rho0s, tol, every, max_steps, log=None, v0s=None):
     """Run every drop to max |rho(t) - rho(t - every)| < tol as one batch;
-    returns (batch, steps, status, seconds).  rho0s: host or device arrays."""
+    returns (batch, steps, status, seconds).  rho0s: host or device arrays.
+    Each drop starts with zero bare velocity (the start of Eq. 41) unless
+    v0s[i] is a pair (vx, vy) of fluid velocities ((None, None): at rest)."""
     import torch
-    host = [r.cpu().numpy() if hasattr(r, "cpu") else r for r in rho0s]
-    b = lbm.Batch(plist, host)
+    b = lbm.Batch(plist, [_host(r) for r in rho0s])
+    for i, v in enumerate(v0s or []):
+        if v is not None:
+            b.set_velocity(i, _host(v[0]), _host(v[1]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, part = 0, 50_000
@@ -56,30 +68,48 @@ def converge(plist, rho0s, tol, every, max_steps, log=None):
     return b, [b.steps_taken(i) for i in range(len(plist))], list(sts), secs
 
 
-def features(member, n, radius, r):
-    """Normalised features (len(r), 5) of nodes at distance r from the centre."""
-    f = np.empty((len(r), 5))
+def geometry(n, radius, nodes):
+    """(r - R, theta) of flat node indices `nodes` of an n x n mesh."""
+    y, x = np.divmod(nodes, n)
+    dx, dy = x - n / 2.0, y - n / 2.0
+    return np.sqrt(dx * dx + dy * dy) - radius, np.arctan2(dy, dx)
+
+
+def features(member, radius, d, theta):
+    """Normalised features (len(d), 7)."""
+    f = np.empty((len(d), 7))
     f[:, 0] = member["T_r"]
     f[:, 1] = radius / R_REF
     f[:, 2] = KAPPA
     f[:, 3] = member["k"]
-    f[:, 4] = r - radius
+    f[:, 4] = d
+    f[:, 5] = np.cos(4.0 * theta)
+    f[:, 6] = np.sin(4.0 * theta)
     return ((f - FEATURE_CENTER) / FEATURE_SCALE).astype(np.float32)
 
 
-def samples(member, p, radius, rho):
-    """Training samples of a converged drop: the row through the centre;
-    target = normalised log density (ln rho - ln rho_g) / (ln rho_l - ln rho_g)."""
+def samples(member, p, radius, rho, ux, uy, stride=2):
+    """Training samples of a converged state (density and fluid velocity):
+    the nodes with both coordinates multiples of `stride`; targets are the
+    normalised log density and the radial and azimuthal velocity in units of
+    U_SCALE."""
     n = p.nx
     g, l = lbm.maxwell(p)
-    row = rho[p.ny // 2]
-    r = np.abs(np.arange(n, dtype=np.float64) - n / 2.0)
-    t = (np.log(row) - np.log(g)) / (np.log(l) - np.log(g))
-    return features(member, n, radius, r), t.astype(np.float32)
+    ys, xs = np.meshgrid(np.arange(0, n, stride), np.arange(0, n, stride), indexing="ij")
+    nodes = (ys * n + xs).ravel()
+    d, th = geometry(n, radius, nodes)
+    r, u, v = rho.ravel()[nodes], ux.ravel()[nodes], uy.ravel()[nodes]
+    c, s = np.cos(th), np.sin(th)
+    t = np.empty((len(nodes), 3))
+    t[:, 0] = (np.log(r) - np.log(g)) / (np.log(l) - np.log(g))
+    t[:, 1] = (u * c + v * s) / U_SCALE
+    t[:, 2] = (-u * s + v * c) / U_SCALE
+    return features(member, radius, d, th), t.astype(np.float32)
 
 
-def training_set(seed, count, n, tol, every, max_steps, log=None):
-    """Converge `count` drops at n x n and return (x, t, info)."""
+def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2):
+    """Converge `count` drops at n x n from the tanh start and return
+    (x, t, info)."""
     members = inputs.warmstart_members(seed, count, **RANGES)
     plist = [drop_params(m, n) for m in members]
     radii = [m["r_frac"] * n for m in members]
@@ -89,8 +119,7 @@ def training_set(seed, count, n, tol, every, max_steps, log=None):
     for i, (m, p, R) in enumerate(zip(members, plist, radii)):
         if sts[i] != lbm.LBM_OK:
             continue
-        rho, _, _ = b.moments(i)
-        x, t = samples(m, p, R, rho)
+        x, t = samples(m, p, R, *b.moments(i), stride=stride)
         xs.append(x)
         ts.append(t)
     b.close()
@@ -103,8 +132,8 @@ def train_network(x, t, *, seed=11, iters=3000, batch=2048, lr=2e-3):
     """Train a fresh network on (x, t) with Adam; returns (MLP, losses, s)."""
     import torch
     net = lbm.MLP(inputs.network_init(seed))
-    xd = torch.from_numpy(x).cuda()
-    td = torch.from_numpy(t).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    td = torch.from_numpy(np.ascontiguousarray(t)).cuda()
     order = torch.from_numpy(inputs.minibatch_order(seed + 1, len(t), batch, iters)).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -113,36 +142,52 @@ def train_network(x, t, *, seed=11, iters=3000, batch=2048, lr=2e-3):
     return net, losses, secs
 
 
-def compare(net, seed, count, n, tol, every, max_steps, log=None):
-    """Unseen drops at n x n from the tanh start and from the warm start (same
-    mass), run to the same criterion.  Returns per-drop steps, wall times
-    (warm start includes building its fields) and the largest differences
-    between the two converged fields."""
+def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True):
+    """Unseen drops at n x n from the tanh start (Eq. 41, zero velocity) and
+    from the warm start (same mass, predicted density and fluid velocity),
+    run to the same criterion; the tanh start with the fluid at rest is run
+    too, for reference.  A drop whose proposed density cannot be mass
+    matched falls back to the tanh start.  Returns per-drop steps, wall
+    times (the warm start's includes building its fields) and the largest
+    differences between the converged states of the two starts."""
     import torch
     members = inputs.warmstart_members(seed, count, **RANGES)
     plist = [drop_params(m, n) for m in members]
     radii = [m["r_frac"] * n for m in members]
     tanh0 = [tanh_start(p, R) for p, R in zip(plist, radii)]
     bt, steps_t, sts_t, secs_t = converge(plist, tanh0, tol, every, max_steps, log)
+    br, steps_r, _, _ = converge(plist, tanh0, tol, every, max_steps, log,
+                                 [(None, None)] * count)
+    br.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    warm0 = [net.warm_start_drop(p, R, float(r.sum())) for p, R, r in zip(plist, radii, tanh0)]
+    rho0, v0, fallback = [], [], 0
+    for p, R, r in zip(plist, radii, tanh0):
+        try:
+            rho, vx, vy = net.warm_start_drop(p, R, float(r.sum()), bf16=bf16)
+            rho0.append(rho)
+            v0.append((vx, vy))
+        except lbm.LBMError:
+            rho0.append(r)
+            v0.append(None)
+            fallback += 1
     torch.cuda.synchronize()
     secs_ws = time.perf_counter() - t0
-    bw, steps_w, sts_w, secs_w = converge(plist, warm0, tol, every, max_steps, log)
+    bw, steps_w, sts_w, secs_w = converge(plist, rho0, tol, every, max_steps, log, v0)
     drho, dv = [], []
-    for i, p in enumerate(plist):
+    for i in range(len(plist)):
         r1, vx1, vy1 = bt.moments(i)
         r2, vx2, vy2 = bw.moments(i)
         drho.append(float(np.abs(r1 - r2).max() / r1.max()))
         dv.append(float(max(np.abs(vx1 - vx2).max(), np.abs(vy1 - vy2).max())))
-    mass = [float(abs(w.sum().item() - r.sum()) / r.sum()) for w, r in zip(warm0, tanh0)]
+    mass = [float(abs(_host(w).sum() - r.sum()) / r.sum()) for w, r in zip(rho0, tanh0)]
     bt.close()
     bw.close()
     return {
         "drops": count, "n": n, "tol": tol, "check_every": every,
-        "steps_tanh": steps_t, "steps_warm": steps_w,
-        "status_tanh": sts_t, "status_warm": sts_w,
+        "inference": "bf16" if bf16 else "fp32",
+        "steps_tanh": steps_t, "steps_warm": steps_w, "steps_tanh_at_rest": steps_r,
+        "status_tanh": sts_t, "status_warm": sts_w, "fallbacks": fallback,
         "seconds_tanh": round(secs_t, 3), "seconds_warm": round(secs_w + secs_ws, 3),
         "seconds_warm_fields": round(secs_ws, 4),
         "max_rel_drho": max(drho), "max_abs_dv": max(dv), "max_rel_mass_gap": max(mass),

@@ -192,3 +192,24 @@ def test_every_batch_column_shape_matches_individual_runs(col_elems, chunk):
         s = _solver(c, col_elems, chunk)
         s.step(40)
         np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)
+
+
+def test_set_velocity_in_a_batch_matches_its_own_context():
+    cases = _mixed_cases()
+    b = _batch(cases)
+    b.step(7)  # odd: the members' state lives in the second buffer
+    solos = [_solver(c) for c in cases]
+    for i, (p, _) in enumerate(cases):
+        u = inputs.uniform01(30 + i, 2 * p.nx * p.ny).reshape(2, p.ny, p.nx)
+        vx, vy = 1e-3 * (u[0] - 0.5), 1e-3 * (u[1] - 0.5)
+        solos[i].step(7)
+        if i % 2:
+            b.set_velocity(i, vx, vy)
+            solos[i].set_velocity(vx, vy)
+        else:
+            b.set_velocity(i)
+            solos[i].set_velocity()
+    b.step(20)
+    for i, s in enumerate(solos):
+        s.step(20)
+        np.testing.assert_array_equal(b.get_state(i), s.get_state(), err_msg="sim %d" % i)

@@ -290,3 +290,33 @@ def test_device_buffers_and_workspace():
     np.testing.assert_array_equal(rb.cpu().numpy(), ra)
     np.testing.assert_array_equal(vxb.cpu().numpy(), vxa)
     np.testing.assert_array_equal(vyb.cpu().numpy(), vya)
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_set_velocity_matches_oracle_and_reports_the_given_velocity(walls):
+    """lbm_set_velocity: f = feq(rho, v - F/(2 rho)) with F of the current
+    density (Eq. 12) against the same construction from the oracle's force;
+    the velocity the solver then reports is the one given."""
+    nx, ny = 96, 72
+    p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                         bc_y=walls)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, _, _ = inputs.droplet(nx, ny, g, l, 18.0, 5.0, seed=21, noise=1e-4)
+    u = inputs.uniform01(22, 2 * nx * ny).reshape(2, ny, nx)
+    vx, vy = 1e-3 * (u[0] - 0.5), 1e-3 * (u[1] - 0.5)
+    s = lbm.Solver(p, rho0)
+    s.set_velocity(vx, vy)
+    f_gpu = s.get_state()
+    r, gx, gy = s.moments()
+    f = oracle.init(op, rho0, np.zeros_like(rho0), np.zeros_like(rho0))
+    _, _, _, _, fx, fy = oracle.moments(op, f, want_force=True)
+    f2 = oracle.init(op, rho0, vx - fx / (2 * rho0), vy - fy / (2 * rho0))
+    err = np.abs(f_gpu - f2).max() / np.abs(f2).max()
+    print("\nset_velocity: f rel err %.2e, |v - given| %.2e" % (
+        err, max(np.abs(gx - vx).max(), np.abs(gy - vy).max())), flush=True)
+    assert err <= 1e-12
+    assert np.abs(r - rho0).max() <= 1e-14 * l
+    assert max(np.abs(gx - vx).max(), np.abs(gy - vy).max()) <= 1e-12 * 1e-3
+    s.set_velocity()  # at rest
+    _, gx, gy = s.moments()
+    assert max(np.abs(gx).max(), np.abs(gy).max()) <= 1e-15

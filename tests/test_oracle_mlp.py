@@ -15,11 +15,11 @@ def _net(seed, scale=0.3):
 
 def _data(seed, n=12):
     rng = np.random.default_rng(seed + 100)
-    return rng.normal(0.0, 1.0, (n, mlp.N_IN)), rng.normal(0.0, 1.0, n)
+    return rng.normal(0.0, 1.0, (n, mlp.N_IN)), rng.normal(0.0, 1.0, (n, mlp.N_OUT))
 
 
 def test_parameter_count():
-    assert mlp.N_PARAMS == 17409
+    assert mlp.N_PARAMS == 7 * 128 + 128 + 128 * 128 + 128 + 3 * 128 + 3 == 17923
 
 
 def test_gradient_matches_central_differences_everywhere():
@@ -45,20 +45,20 @@ def test_gradient_matches_central_differences_everywhere():
 
 def test_gradient_with_silent_hidden_layer():
     """W2 = 0, b2 = 0: a2 = 0, so y = b3 for every sample, dL/db3 =
-    2 mean(b3 - t) and dL/dW3 = 0, dL/dW1 = dL/db1 = 0 (W2 blocks the path)."""
+    2 mean(b3 - t) per output, dL/dW3 = 0, dL/dW1 = dL/db1 = 0 (W2 blocks the
+    path) and dL/db2 = W3^T dL/db3 (tanh'(0) = 1)."""
     w = _net(2)
     W1, b1, W2, b2, W3, b3 = mlp.unpack(w)
     W2[:] = 0.0
     b2[:] = 0.0
     x, t = _data(2)
     y, _, _ = mlp.forward(w, x)
-    assert np.all(y == b3[0])
+    assert np.all(y == b3)
     _, g = mlp.grad(w, x, t)
     gW1, gb1, gW2, gb2, gW3, gb3 = mlp.unpack(g)
-    assert gb3[0] == pytest.approx(2.0 * np.mean(b3[0] - t), rel=1e-14)
+    np.testing.assert_allclose(gb3, 2.0 * np.mean(b3 - t, axis=0), rtol=1e-14)
     assert np.all(gW3 == 0.0) and np.all(gW1 == 0.0) and np.all(gb1 == 0.0)
-    # dL/db2_j = sum_s dy_s W3_j (tanh'(0) = 1)
-    assert np.allclose(gb2, gb3[0] * W3, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(gb2, gb3 @ W3, rtol=1e-12, atol=1e-15)
 
 
 def test_adam_first_steps_move_by_the_learning_rate():
@@ -109,6 +109,10 @@ def test_density_map_and_mass_match():
     d = f[:, 4] * mlp.FEATURE_SCALE[4]
     y = 0.5 * (1.0 - np.tanh(d / 3.0))
     rho = mlp.density_from_output(y, g, l).reshape(64, 64)
+    # angle features: node (x, y) = (40, 32) lies on theta = 0, (32, 40) on pi/2
+    assert f[32 * 64 + 40, 5] == pytest.approx(1.0) and f[32 * 64 + 40, 6] == pytest.approx(0.0)
+    assert f[40 * 64 + 32, 5] == pytest.approx(1.0) and abs(f[40 * 64 + 32, 6]) < 1e-12
+    assert f[40 * 64 + 40, 5] == pytest.approx(-1.0)  # theta = pi/4
     target = rho.sum() * (1.0 + 1e-3)
     r2 = mlp.mass_match(rho, target, g, l)
     assert r2.sum() == pytest.approx(target, rel=1e-14)
@@ -117,3 +121,27 @@ def test_density_map_and_mass_match():
     # the features: centre node has r - R = -R; normalisation as documented
     assert f[32 * 64 + 32, 4] == pytest.approx(-20.0 / 8.0)
     assert f[0, 0] == pytest.approx(0.0) and f[0, 1] == pytest.approx((20 / 256 - 0.25) / 0.1)
+
+
+def test_velocity_from_output_rotates_the_polar_components():
+    th = np.array([0.0, np.pi / 2, np.pi, -np.pi / 2])
+    y = np.zeros((4, 3))
+    y[:, 1] = 2.0   # radial outwards, 2e-3
+    ux, uy = mlp.velocity_from_output(y, th)
+    np.testing.assert_allclose(ux, [2e-3, 0.0, -2e-3, 0.0], atol=1e-18)
+    np.testing.assert_allclose(uy, [0.0, 2e-3, 0.0, -2e-3], atol=1e-18)
+    y[:, 1], y[:, 2] = 0.0, 1.0  # azimuthal, counter-clockwise
+    ux, uy = mlp.velocity_from_output(y, th)
+    np.testing.assert_allclose(ux, [0.0, -1e-3, 0.0, 1e-3], atol=1e-18)
+    np.testing.assert_allclose(uy, [1e-3, 0.0, -1e-3, 0.0], atol=1e-18)
+
+
+def test_symmetric_outputs_are_even_and_odd_under_reflection():
+    w = _net(6, scale=0.2)
+    x, _ = _data(6, n=40)
+    xm = x.copy()
+    xm[:, -1] = -xm[:, -1]
+    for bf16 in (False, True):
+        y, ym = mlp.symmetric_outputs(w, x, bf16), mlp.symmetric_outputs(w, xm, bf16)
+        np.testing.assert_allclose(ym[:, :2], y[:, :2], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(ym[:, 2], -y[:, 2], rtol=0, atol=1e-15)
