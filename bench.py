@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D2Q9 FP64) + % peak HBM BW; sweep/warm-start time-to-converge vs plain"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per node of each kernel (FP64):
-#   row pass A: read f (9 x 8), write rho and d2/dx2 rho (2 x 8)
-#   column pass B: read rho, d2/dx2 rho; write mu, F_y
+#   row pass A: read f (9 x 8), write rho and the row part of mu (2 x 8)
+#   column pass B: read rho and the row part of mu; write mu, F_y
 #   row pass C: read f, mu, F_y; write f (9 x 8)
 PASS_NAMES = ["rows_rho", "cols_mu", "rows_collide"]
 PASS_BYTES = [88, 32, 160]

@@ -26,7 +26,7 @@ struct lbm_ctx {
     size_t N = 0;
     double *f[2] = {nullptr, nullptr};
     int cur = 0;  // f[cur] holds the current state
-    double *rho = nullptr, *dxx = nullptr, *mu = nullptr, *fy = nullptr;
+    double *rho = nullptr, *mux = nullptr, *mu = nullptr, *fy = nullptr;
     double *prev = nullptr, *obs = nullptr, *partial = nullptr, *red = nullptr;
     int red_blocks = 1;
     int64_t steps = 0;
@@ -56,7 +56,7 @@ Layout layout_for(const lbm_params *p, int red_blocks)
     L.field = align256(N * sizeof(double));
     L.partial = align256(2 * (size_t)red_blocks * sizeof(double));
     L.red = align256(2 * sizeof(double));
-    // f A/B, rho, dxx, mu, fy, prev, 3 observation planes, partials, result
+    // f A/B, rho, mux, mu, fy, prev, 3 observation planes, partials, result
     L.total = 2 * L.f + 8 * L.field + L.partial + L.red;
     return L;
 }
@@ -209,7 +209,7 @@ void carve(lbm_ctx *c, int red_blocks)
     m += L.f;
     c->f[1] = (double *)m;
     m += L.f;
-    double **fields[] = {&c->rho, &c->dxx, &c->mu, &c->fy, &c->prev};
+    double **fields[] = {&c->rho, &c->mux, &c->mu, &c->fy, &c->prev};
     for (double **q : fields) {
         *q = (double *)m;
         m += L.field;
@@ -226,8 +226,8 @@ lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
     for (int64_t s = 0; s < n; ++s) {
         const double *fc = c->f[c->cur];
         double *fn = c->f[1 - c->cur];
-        HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream));
-        HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream));
+        HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream));
+        HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
         HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream));
         c->cur = 1 - c->cur;
         c->steps += 1;
@@ -239,8 +239,8 @@ lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
 lbm_status enqueue_fields(lbm_ctx *c)
 {
     const double *fc = c->f[c->cur];
-    HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream));
-    HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream));
+    HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream));
+    HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
     return LBM_OK;
 }
 
@@ -532,13 +532,13 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
     HIP_OR(c, hipEventCreate(&e1));
     const double *fc = c->f[c->cur];
     double *fn = c->f[1 - c->cur];
-    hipError_t err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
-    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+    hipError_t err = launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream);
+    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
     for (int q = 0; q < 3 && err == hipSuccess; ++q) {
         err = hipEventRecord(e0, c->stream);
         for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
-            if (q == 0) err = launch_rows_rho(c->kp, fc, c->rho, c->dxx, c->stream);
-            if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+            if (q == 0) err = launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream);
+            if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
             if (q == 2) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream);
         }
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
@@ -562,7 +562,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     if (repeats <= 0) return fail(c, LBM_E_INVALID, "repeats must be positive");
     // the column pass reads rho and d2/dx2 rho and writes mu and F_y only,
     // so timing it repeatedly leaves the state untouched
-    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->rho, c->dxx, c->stream));
+    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->rho, c->mux, c->stream));
     hipEvent_t e0, e1;
     HIP_OR(c, hipEventCreate(&e0));
     HIP_OR(c, hipEventCreate(&e1));
@@ -578,10 +578,10 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         if (kp.cols_per_block != w) continue;  // does not fit one block
         // the general kernel ignores the chunk length: time it once
         if (!kp.use_iir_cols && ch != cand_c[0]) continue;
-        err = launch_cols_mu(kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+        err = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
         for (int r = 0; r < repeats && err == hipSuccess; ++r)
-            err = launch_cols_mu(kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+            err = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float t = 0.f;
@@ -602,7 +602,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     // collision pass: populations held in registers or read twice.  It reads
     // the current f, mu and F_y and writes only the spare buffer, so the state
     // is untouched; mu and F_y are refreshed first with the chosen shape.
-    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->dxx, c->mu, c->fy, c->stream);
+    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
     double best_row = INFINITY;
     int best_keep = c->kp.row_keep;
     for (int keep = 0; keep < 2 && err == hipSuccess; ++keep) {
@@ -893,7 +893,7 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
     if (hipGetDevice(&b->device) != hipSuccess) return give_up(LBM_E_DEVICE, "no HIP device");
     if (hipStreamCreate(&b->stream) != hipSuccess) return give_up(LBM_E_DEVICE, "hipStreamCreate");
 
-    // one allocation: per simulation f A/B, rho, dxx, mu, fy, prev, partials
+    // one allocation: per simulation f A/B, rho, mux, mu, fy, prev, partials
     size_t total = 0;
     std::vector<size_t> off(nsims);
     b->N.resize(nsims);
@@ -919,7 +919,7 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         m += align256(9 * N * sizeof(double));
         q.f[1] = (double *)m;
         m += align256(9 * N * sizeof(double));
-        double **planes[] = {&q.rho, &q.dxx, &q.mu, &q.fy, &b->prev[s]};
+        double **planes[] = {&q.rho, &q.mux, &q.mu, &q.fy, &b->prev[s]};
         for (double **pl : planes) {
             *pl = (double *)m;
             m += align256(N * sizeof(double));
@@ -946,8 +946,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         hipError_t e = hipMemcpy(q.rho, rho0[s], N * sizeof(double), hipMemcpyHostToDevice);
         const double *dux = nullptr, *duy = nullptr;
         if (e == hipSuccess && ux0 && ux0[s]) {
-            e = hipMemcpy(q.dxx, ux0[s], N * sizeof(double), hipMemcpyHostToDevice);
-            dux = q.dxx;
+            e = hipMemcpy(q.mux, ux0[s], N * sizeof(double), hipMemcpyHostToDevice);
+            dux = q.mux;
         }
         if (e == hipSuccess && uy0 && uy0[s]) {
             e = hipMemcpy(q.mu, uy0[s], N * sizeof(double), hipMemcpyHostToDevice);
@@ -1126,8 +1126,8 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx,
     double *obs = nullptr;
     BHIP_OR(b, hipMalloc(&obs, 3 * N * sizeof(double)));
     const double *fc = q.f[sim_parity(b, sim)];
-    hipError_t e = launch_rows_rho(k, fc, q.rho, q.dxx, b->stream);
-    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.dxx, q.mu, q.fy, b->stream);
+    hipError_t e = launch_rows_rho(k, fc, q.rho, q.mux, b->stream);
+    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
         e = launch_rows_observe(k, fc, q.mu, q.fy, obs, obs + N, obs + 2 * N, nullptr, b->stream);
     double *outs[3] = {rho, vx, vy};
@@ -1166,8 +1166,8 @@ lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, c
     BHIP_OR(b, hipMalloc(&tmp, 3 * N * sizeof(double)));
     double *fx = tmp, *ux = tmp + N, *uy = tmp + 2 * N;
     double *fc = q.f[sim_parity(b, sim)];
-    hipError_t e = launch_rows_rho(k, fc, q.rho, q.dxx, b->stream);
-    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.dxx, q.mu, q.fy, b->stream);
+    hipError_t e = launch_rows_rho(k, fc, q.rho, q.mux, b->stream);
+    if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
         e = launch_rows_observe(k, fc, q.mu, q.fy, nullptr, nullptr, nullptr, fx, b->stream);
     if (e == hipSuccess)

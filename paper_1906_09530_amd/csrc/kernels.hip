@@ -144,7 +144,7 @@ template <bool FAST, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
                                                                const double *__restrict__ f,
                                                                double *__restrict__ rho_out,
-                                                               double *__restrict__ dxx_out)
+                                                               double *__restrict__ mux_out)
 {
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
@@ -154,6 +154,7 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
     double *bA = smem, *bB = smem + p.rows_per_block * nx;
     const LineMap<FAST> m{nx, rows, false, false};
     const Elems E = make_elems(m);
+    double rr[kElemsPerThread];
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
@@ -161,18 +162,22 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
         double fi[9];
         load9(f, N, node, fi);
         const double r = sum9(fi);
+        rr[k] = r;
         bA[E.e[k]] = r;
         rho_out[node] = r;
+        if (p.kappa_zero) mux_out[node] = p.k2 * mu0_capped(p, r);
     }
     if (p.kappa_zero) return;  // uniform: the Laplacian is not used
     __syncthreads();
     double d1[kElemsPerThread], d2[kElemsPerThread];
     double *res = cfm_solve(p, m, E, bA, bB, 1.0, d1);
     cfm_solve(p, m, E, res, res == bA ? bB : bA, -1.0, d2);
+    // the row part of the chemical potential, Eq. 33: k^2 psi'(rho) - kappa d2rho/dx2
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
-        dxx_out[(size_t)(y0 + E.l[k]) * nx + E.j[k]] = d2[k];
+        const size_t node = (size_t)(y0 + E.l[k]) * nx + E.j[k];
+        mux_out[node] = p.k2 * mu0_capped(p, rr[k]) - p.kappa * d2[k];
     }
 }
 
@@ -190,7 +195,7 @@ __device__ __forceinline__ int strip_of_block(const KParams &p)
 template <bool FAST, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_cols_mu(KParams p,
                                                               const double *__restrict__ rho,
-                                                              const double *__restrict__ dxx,
+                                                              const double *__restrict__ mux,
                                                               double *__restrict__ mu_out,
                                                               double *__restrict__ fy_out)
 {
@@ -217,8 +222,8 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu(KParams p,
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
         const size_t node = (size_t)E.j[k] * nx + x0 + E.l[k];
-        double mu = p.k2 * mu0_capped(p, r[k]);
-        if (!p.kappa_zero) mu -= p.kappa * (dxx[node] + dyy[k]);
+        double mu = mux[node];
+        if (!p.kappa_zero) mu -= p.kappa * dyy[k];
         mu_out[node] = mu;
         bA[E.e[k]] = mu;
     }
@@ -458,21 +463,21 @@ static bool col_fast(const KParams &p) { return p.ny >= kFastMinLine; }
             hipLaunchKernelGGL((K<false, 1024 __VA_OPT__(,) __VA_ARGS__>), GRID);\
     } while (0)
 
-hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *dxx,
+hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *mux,
                            hipStream_t s)
 {
-    if (p.use_iir_rows) return launch_rows_rho_iir(p, f, rho, dxx, s);
-#define GRID dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, rho, dxx
+    if (p.use_iir_rows) return launch_rows_rho_iir(p, f, rho, mux, s);
+#define GRID dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, rho, mux
     CPLBM_DISPATCH(k_rows_rho, row_fast(p), p.row_threads);
 #undef GRID
     return hipGetLastError();
 }
 
-hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *dxx, double *mu,
+hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux, double *mu,
                           double *fy, hipStream_t s)
 {
-    if (p.use_iir_cols) return launch_cols_mu_iir(p, rho, dxx, mu, fy, s);
-#define GRID dim3(col_blocks(p)), dim3(p.col_threads), col_lds(p), s, p, rho, dxx, mu, fy
+    if (p.use_iir_cols) return launch_cols_mu_iir(p, rho, mux, mu, fy, s);
+#define GRID dim3(col_blocks(p)), dim3(p.col_threads), col_lds(p), s, p, rho, mux, mu, fy
     CPLBM_DISPATCH(k_cols_mu, col_fast(p), p.col_threads);
 #undef GRID
     return hipGetLastError();

@@ -41,11 +41,13 @@ constexpr int kIirRowChunk = 4;
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
 
-// Pass A over rows: rho = sum f, d/dx rho, d2/dx2 rho.  Writes rho, dxx.
-hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *dxx,
+// Pass A over rows: rho = sum f and the row part of the chemical potential
+// (Eq. 33), mux = k^2 psi'(rho) - kappa d2rho/dx2 (k^2 psi'(rho) when kappa = 0).
+hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *mux,
                            hipStream_t s);
-// Pass B over columns: d/dy rho, d2/dy2 rho, mu (Eq. 33), d/dy mu, F_y (Eq. 12).
-hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *dxx, double *mu,
+// Pass B over columns: d/dy rho, d2/dy2 rho, mu = mux - kappa d2rho/dy2 (Eq. 33),
+// d/dy mu, F_y (Eq. 12).
+hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux, double *mu,
                           double *fy, hipStream_t s);
 // Pass C over rows: d/dx rho, d/dx mu, F_x, collision and streaming f -> fout.
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
@@ -78,7 +80,7 @@ void set_col_shape(KParams *p, int width, int chunk);
 // Device-side buffers of one mesh of a batch.
 struct SimBuffers {
     double *f[2];
-    double *rho, *dxx, *mu, *fy;
+    double *rho, *mux, *mu, *fy;
 };
 // One workgroup of a batched pass: the mesh and its first row or column.
 struct WorkItem {
@@ -102,9 +104,9 @@ hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
 // Fast-path kernels (kernels_iir.hip) and their eligibility.
 bool iir_rows_ok(const KParams &p);
 bool iir_cols_ok(const KParams &p, int chunk, int width);
-hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *dxx,
+hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *mux,
                                hipStream_t s);
-hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *dxx, double *mu,
+hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
                               double *fy, hipStream_t s);
 hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,
                                    const double *fy, double *fout, double *o_rho, double *o_vx,

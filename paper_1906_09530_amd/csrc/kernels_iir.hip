@@ -158,10 +158,11 @@ __device__ __forceinline__ Chunk<LC> row_chunk(const KParams &p, int rows)
 
 constexpr int kRowLC = 4;
 
-// Pass A on rows [y0, y0 + rows_per_block) of one mesh.
+// Pass A on rows [y0, y0 + rows_per_block) of one mesh: rho, and the row part
+// of the chemical potential of Eq. 33, k^2 psi'(rho) - kappa d2rho/dx2.
 __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const double *__restrict__ f,
                                               double *__restrict__ rho_out,
-                                              double *__restrict__ dxx_out)
+                                              double *__restrict__ mux_out)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
@@ -186,19 +187,32 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
         for (int k = 0; k < LC; ++k) rho[k] = acc[k];
         vstore<LC>(rho_out + base, rho);
     }
-    if (p.kappa_zero) return;  // uniform: the Laplacian is not used
+    // bulk part first: its transcendental work overlaps the solves' barriers
+    double mx[LC];
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) mx[k] = p.k2 * mu0_capped(p, rho[k]);
+    }
+    if (p.kappa_zero) {  // uniform: the Laplacian is not used
+        if (m.ok) vstore<LC>(mux_out + base, mx);
+        return;
+    }
     double d1[LC], d2[LC];
     iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, d1);
     iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, d1, -1.0, vbuf, cP, cB, d2);
-    if (m.ok) vstore<LC>(dxx_out + base, d2);
+    if (m.ok) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) mx[k] -= p.kappa * d2[k];
+        vstore<LC>(mux_out + base, mx);
+    }
 }
 
 template <int MAXT>
 __global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ f,
                                                        double *__restrict__ rho_out,
-                                                       double *__restrict__ dxx_out)
+                                                       double *__restrict__ mux_out)
 {
-    rows_rho_body(p, blockIdx.x * p.rows_per_block, f, rho_out, dxx_out);
+    rows_rho_body(p, blockIdx.x * p.rows_per_block, f, rho_out, mux_out);
 }
 
 __device__ __forceinline__ int strip_of_block(const KParams &p)
@@ -215,7 +229,7 @@ __device__ __forceinline__ int strip_of_block(const KParams &p)
 template <int LC>
 __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
                                              const double *__restrict__ rho,
-                                             const double *__restrict__ dxx,
+                                             const double *__restrict__ mux,
                                              double *__restrict__ mu_out,
                                              double *__restrict__ fy_out)
 {
@@ -246,8 +260,8 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
 #pragma unroll
         for (int k = 0; k < LC; ++k) {
             const size_t node = (size_t)(j0 + k) * nx + col;
-            double v = p.k2 * mu0_capped(p, r[k]);
-            if (!p.kappa_zero) v -= p.kappa * (dxx[node] + dyy[k]);
+            double v = mux[node];
+            if (!p.kappa_zero) v -= p.kappa * dyy[k];
             mu[k] = v;
             mu_out[node] = v;
         }
@@ -262,11 +276,11 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
 
 template <int LC, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *__restrict__ rho,
-                                                      const double *__restrict__ dxx,
+                                                      const double *__restrict__ mux,
                                                       double *__restrict__ mu_out,
                                                       double *__restrict__ fy_out)
 {
-    cols_mu_body<LC>(p, strip_of_block(p) * p.cols_per_block, rho, dxx, mu_out, fy_out);
+    cols_mu_body<LC>(p, strip_of_block(p) * p.cols_per_block, rho, mux, mu_out, fy_out);
 }
 
 // Pass C on rows [y0, y0 + rows_per_block) of one mesh.
@@ -451,7 +465,7 @@ __global__ __launch_bounds__(256) void kb_rows_rho(const KParams *__restrict__ k
 {
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
-    rows_rho_body(kps[w.sim], w.start, b.f[parity], b.rho, b.dxx);
+    rows_rho_body(kps[w.sim], w.start, b.f[parity], b.rho, b.mux);
 }
 
 template <int LC, int MAXT>
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(MAXT) void kb_cols_mu(const KParams *__restrict__ k
 {
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
-    cols_mu_body<LC>(kps[w.sim], w.start, b.rho, b.dxx, b.mu, b.fy);
+    cols_mu_body<LC>(kps[w.sim], w.start, b.rho, b.mux, b.mu, b.fy);
 }
 
 __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict__ kps,
@@ -556,21 +570,21 @@ static int col_threads_iir(const KParams &p) { return p.cols_per_block * (p.ny /
             hipLaunchKernelGGL(K1024, GRIDARGS);                                           \
     } while (0)
 
-hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *dxx,
+hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *mux,
                                hipStream_t s)
 {
     const int T = row_threads_iir(p);
-#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, rho, dxx
+#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, rho, mux
     CPLBM_IIR_THREADS(T, k_rows_rho_iir<256>, k_rows_rho_iir<1024>, ARGS);
 #undef ARGS
     return hipGetLastError();
 }
 
-hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *dxx, double *mu,
+hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
                               double *fy, hipStream_t s)
 {
     const int T = col_threads_iir(p);
-#define ARGS dim3(col_blocks(p)), dim3(T), col_lds_iir(p), s, p, rho, dxx, mu, fy
+#define ARGS dim3(col_blocks(p)), dim3(T), col_lds_iir(p), s, p, rho, mux, mu, fy
     switch (p.col_lc) {
     case 4: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<4, 256>), (k_cols_mu_iir<4, 1024>), ARGS); break;
     case 8: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<8, 256>), (k_cols_mu_iir<8, 1024>), ARGS); break;

@@ -55,15 +55,22 @@ __device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
     }
     case 1:
     case 2: {  // Redlich-Kwong, Soave-Redlich-Kwong; eos_c1 = A / b
-        const double iv = 1.0 / (1.0 - br);
-        m = RT * log(rho * iv) + RT * iv - p.eos_c1 * log(1.0 + br) - A * rho / (1.0 + br);
+        // one reciprocal for both denominators, 1 - b rho and 1 + b rho
+        const double d1 = 1.0 - br, d2 = 1.0 + br;
+        const double inv = 1.0 / (d1 * d2);
+        const double iv = d2 * inv;
+        m = RT * log(rho * iv) + RT * iv - p.eos_c1 * log(d2) - A * rho * (d1 * inv);
         break;
     }
     case 3: {  // Peng-Robinson; eos_c1 = A / (2 sqrt(2) b)
+        // one reciprocal for the three denominators 1 - b rho, sqrt2 + 1 - b rho
+        // and 1 + 2 b rho - (b rho)^2 (all positive inside the domain)
         const double s2 = 1.4142135623730950488;
-        const double iv = 1.0 / (1.0 - br);
-        m = RT * log(rho * iv) - p.eos_c1 * log((s2 - 1.0 + br) / (s2 + 1.0 - br)) + RT * iv -
-            A * rho / (1.0 + 2.0 * br - br * br);
+        const double d1 = 1.0 - br, d2 = s2 + 1.0 - br, d3 = 1.0 + 2.0 * br - br * br;
+        const double inv = 1.0 / (d1 * d2 * d3);
+        const double iv = d2 * d3 * inv;
+        m = RT * log(rho * iv) - p.eos_c1 * log((s2 - 1.0 + br) * (d1 * d3 * inv)) + RT * iv -
+            A * rho * (d1 * d2 * inv);
         break;
     }
     default: {  // Carnahan-Starling
