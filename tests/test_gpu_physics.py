@@ -12,7 +12,7 @@ by the oracle):
 * drops, same settings, R = 32 ... 96 (radius at least four interface
   widths): the pressure jump k^2 [p0(rho_in) - p0(rho_out)] times the
   equimolar radius is the same for every drop to 3 % (Laplace's law, measured
-  0.4 %); the surface tension it implies exceeds the continuum
+  1.2 %); the surface tension it implies exceeds the continuum
   sigma = k sqrt(kappa) sigma_1 by 1.77x.  The flat interface shows why: the
   forced lattice carries a bare velocity u = -F/(2 rho) inside the interface,
   whose momentum flux F F/(4 rho) adds normal stress; summed over the
