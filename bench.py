@@ -12,9 +12,12 @@ roofline entry of the dominant kernel (algorithmic bytes / its average
 duration, HIP events on the solver's stream) and the CPU oracle timed on a
 bounded sample of the same workload.  The "sweep" entry times a batched
 sweep of simulations of uneven size to convergence against running each on
-its own (the plain method).
+its own (the plain method); the "warm_start" entry trains the warm-start
+network on solver-converged drops and compares steps and time to converge
+from its proposal and from the tanh start.
 
     python bench.py [--gpus 1] [--steps 20000] [--warmup 200] [--sweep small|full|none]
+                    [--warmstart small|full|none]
 """
 import argparse
 import json
@@ -153,6 +156,44 @@ def sweep_bench(lbm, inputs, which):
     }
 
 
+# Learned warm start: CS drops (warmstart.RANGES), kappa = 0.1, tau = 1;
+# training drops converged by the solver, then unseen drops run from the tanh
+# start and from the warm start to the same criterion.
+WARM = {"small": dict(train=96, train_n=128, eval=8, eval_n=128),
+        "full": dict(train=192, train_n=256, eval=8, eval_n=512)}
+
+
+def warmstart_bench(which):
+    from paper_1906_09530_amd import warmstart
+    cfg = WARM[which]
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    log("warm start %s: converging %d training drops at %d^2" % (which, cfg["train"],
+                                                               cfg["train_n"]))
+    x, t, info = warmstart.training_set(5, cfg["train"], cfg["train_n"], 1e-12, 100, 3_000_000,
+                                        log=log)
+    net, losses, secs = warmstart.train_network(x, t)
+    log("  trained in %.1f s (final loss %.3e)" % (secs, float(losses[-20:].mean())))
+    # radii of the unseen drops drawn from the training drops' range
+    res = warmstart.compare(net, 55, cfg["eval"], cfg["eval_n"], 1e-12, 100, 3_000_000, log=log,
+                            bf16=False, r_scale=cfg["train_n"] / cfg["eval_n"])
+    net.close()
+    st, sw = sum(res["steps_tanh"]), sum(res["steps_warm"])
+    return {
+        "set": which, "training": info, "samples": int(len(t)), "train_s": round(secs, 2),
+        "eval_drops": cfg["eval"], "eval_n": cfg["eval_n"],
+        "eval_radius_range": [round(r * cfg["train_n"], 1) for r in (0.15, 0.35)],
+        "tol": 1e-12, "check_every": 100,
+        "inference": res["inference"],
+        "steps_tanh": st, "steps_warm": sw, "steps_ratio": round(sw / st, 4),
+        "steps_tanh_fluid_at_rest": sum(res["steps_tanh_at_rest"]),
+        "seconds_tanh": res["seconds_tanh"], "seconds_warm": res["seconds_warm"],
+        "all_converged": all(s == 0 for s in res["status_tanh"] + res["status_warm"]),
+        "fallbacks": res["fallbacks"],
+        "max_rel_drho_vs_tanh_solution": res["max_rel_drho"],
+        "max_abs_dv_vs_tanh_solution": res["max_abs_dv"],
+    }
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -191,6 +232,10 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=1000,
                     help="steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warmstart", choices=["small", "full", "none"], default="small",
+                    help="learned warm start vs tanh start (steps and time to converge): 96 "
+                         "training drops at 128^2, 8 unseen at 128^2 (small); 192 at 256^2, 8 "
+                         "unseen at 512^2 (full, minutes); or none")
     ap.add_argument("--sweep", choices=["small", "full", "none"], default="small",
                     help="batched sweep vs one run per member (time to converge): 16 members "
                          "up to 256^2 (small), 64 members up to 512^2 (full, minutes), or none")
@@ -265,6 +310,7 @@ def main():
 
     traffic = measured_traffic(PASS_NAMES[dom])
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
+    warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     out = {
         "metric": METRIC,
@@ -309,6 +355,7 @@ def main():
                   "rho_corner": float(outside), "max_speed": float(np.hypot(vx, vy).max()),
                   "rho_g_maxwell": rho_g, "rho_l_maxwell": rho_l},
         "sweep": sweep,
+        "warm_start": warm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

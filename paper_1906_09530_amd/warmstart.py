@@ -128,32 +128,48 @@ def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2):
         "steps_max": max(steps), "seconds": round(secs, 2)}
 
 
-def train_network(x, t, *, seed=11, iters=3000, batch=2048, lr=2e-3):
-    """Train a fresh network on (x, t) with Adam; returns (MLP, losses, s)."""
+def train_network(x, t, *, seed=11, phases=((6000, 2e-3), (6000, 4e-4)), batch=4096,
+                  density_weight=10.0):
+    """Train a fresh network on (x, t) with Adam, one run of minibatches per
+    (iterations, learning rate) phase.  The density output is trained scaled
+    by density_weight (it needs more relative accuracy than the velocity) and
+    the weight is folded back into the last layer afterwards, so the returned
+    network predicts the quantities of include/lbm_warmstart.h.  Returns
+    (MLP, losses of the last phase, seconds)."""
     import torch
     net = lbm.MLP(inputs.network_init(seed))
+    tw = np.array(t, dtype=np.float32)
+    tw[:, 0] *= density_weight
     xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
-    td = torch.from_numpy(np.ascontiguousarray(t)).cuda()
-    order = torch.from_numpy(inputs.minibatch_order(seed + 1, len(t), batch, iters)).cuda()
+    td = torch.from_numpy(tw).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = net.train(xd, td, order, batch, lr=lr)
+    for i, (iters, lr) in enumerate(phases):
+        order = torch.from_numpy(inputs.minibatch_order(seed + 1 + i, len(tw), batch, iters))
+        losses = net.train(xd, td, order.cuda(), batch, lr=lr)
     secs = time.perf_counter() - t0
+    w = net.get_params()
+    off_w3 = 7 * 128 + 128 + 128 * 128 + 128  # W3 row 0, then b3[0] after W3
+    w[off_w3:off_w3 + 128] /= density_weight
+    w[off_w3 + 3 * 128] /= density_weight
+    net.set_params(w)
     return net, losses, secs
 
 
-def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True):
+def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_scale=1.0):
     """Unseen drops at n x n from the tanh start (Eq. 41, zero velocity) and
     from the warm start (same mass, predicted density and fluid velocity),
     run to the same criterion; the tanh start with the fluid at rest is run
     too, for reference.  A drop whose proposed density cannot be mass
     matched falls back to the tanh start.  Returns per-drop steps, wall
     times (the warm start's includes building its fields) and the largest
-    differences between the converged states of the two starts."""
+    differences between the converged states of the two starts.  r_scale
+    scales the drawn radii (to keep a larger mesh's drops within the radii the
+    network was trained on)."""
     import torch
     members = inputs.warmstart_members(seed, count, **RANGES)
     plist = [drop_params(m, n) for m in members]
-    radii = [m["r_frac"] * n for m in members]
+    radii = [r_scale * m["r_frac"] * n for m in members]
     tanh0 = [tanh_start(p, R) for p, R in zip(plist, radii)]
     bt, steps_t, sts_t, secs_t = converge(plist, tanh0, tol, every, max_steps, log)
     br, steps_r, _, _ = converge(plist, tanh0, tol, every, max_steps, log,
