@@ -366,3 +366,15 @@ def test_splash_is_galilean_invariant_between_sliding_walls():
         np.abs(h0 - h1)[ok].max(), ok.sum()), flush=True)
     assert ok.sum() >= 0.9 * nx
     assert np.abs(h0 - h1)[ok].max() <= 1.0
+
+
+@pytest.mark.parametrize("eos", [lbm.EOS_VDW, lbm.EOS_RK, lbm.EOS_RKS])
+def test_other_equations_of_state(eos):
+    """The van der Waals, Redlich-Kwong and Soave-Redlich-Kwong chemical
+    potentials (Eqs. 15, 17; RKS with the acentric factor 0.344), a drop at
+    T_r = 0.6 with the upper limit 6, 300 steps."""
+    nx, ny = 96, 80
+    p, op = _case_params(eos, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 20.0, 6.0, seed=3, noise=1e-6)
+    _run_case("eos%d" % eos, p, op, rho0, ux0, uy0, [100, 300])
