@@ -250,8 +250,16 @@ def main():
         b = torch.empty_like(a)
         for _ in range(5):
             b.copy_(a)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            b.copy_(a)
+        ev1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calib_bytes_per_dispatch": n * 8}), flush=True)
+        ms = ev0.elapsed_time(ev1) / 10
+        print(json.dumps({"copy_calib_bytes_per_dispatch": n * 8,
+                          "copy_GB_s_read_plus_write": round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)}),
+              flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is a single-GPU build "
