@@ -194,6 +194,23 @@ def warmstart_bench(which):
     }
 
 
+def copy_bandwidth(torch, nbytes, reps=20):
+    """Read + write GB/s of the runtime's own device-to-device copy of
+    nbytes / 2 (so that it moves nbytes per dispatch, like the kernel it is
+    compared with): the rate a plain streaming kernel reaches on this device."""
+    n = nbytes // 16
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * n * 8 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -309,6 +326,7 @@ def main():
     gbs = [PASS_BYTES[i] * NX * NY / (pass_ms[i] * 1e-3) / 1e9 for i in range(3)]
     dom = int(np.argmax(pass_ms))
 
+    copy_gbs = copy_bandwidth(torch, PASS_BYTES[dom] * NX * NY)
     r, vx, vy = s.moments()
     finite = bool(np.isfinite(r).all())
     inside = r[NY // 2, NX // 2]
@@ -353,6 +371,7 @@ def main():
                                        round(traffic / (PASS_BYTES[dom] * NX * NY), 4)),
             "bytes_per_node": PASS_BYTES[dom],
             "avg_ms": round(pass_ms[dom], 6),
+            "device_copy_GB_s": round(copy_gbs, 1),
         },
         "kernels": {PASS_NAMES[i]: {"avg_ms": round(pass_ms[i], 6), "GB_s": round(gbs[i], 1),
                                     "bytes_per_node": PASS_BYTES[i]} for i in range(3)},
