@@ -32,17 +32,19 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D2Q9 FP64) + % peak HBM BW; sweep/warm-start time-to-converge vs plain"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per node of each kernel (FP64):
-#   row pass A: read f (9 x 8), write rho and the row part of mu (2 x 8)
+#   row pass A: read the three density groups of the state (3 x 8), write rho
+#     and the row part of mu (2 x 8)
 #   column pass B: read rho and the row part of mu; write mu, F_y
-#   row pass C: read f, mu, F_y; write f (9 x 8)
+#   row pass C: read f (9 x 8), mu, F_y; write f (9 x 8) and its three
+#     density groups (3 x 8)
 PASS_NAMES = ["rows_rho", "cols_mu", "rows_collide"]
-PASS_BYTES = [88, 32, 160]
+PASS_BYTES = [40, 32, 184]
 
 NX = NY = 1024
 CFG = dict(T_r=0.5, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0, radius=200.0, width=10.0)
 
 
-KERNEL_SOURCES = ["kernels.hip", "kernels_iir.hip", "kernels.hpp", "physics.hpp"]
+KERNEL_SOURCES = ["kernels.hip", "kernels_iir.hip", "kernels.hpp", "physics.hpp", "lnx.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_pr1024.json")
 
 

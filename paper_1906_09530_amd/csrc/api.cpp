@@ -25,7 +25,8 @@ struct lbm_ctx {
     void *mem = nullptr;
     size_t N = 0;
     double *f[2] = {nullptr, nullptr};
-    int cur = 0;  // f[cur] holds the current state
+    double *g[2] = {nullptr, nullptr};  // density groups of f[0], f[1]
+    int cur = 0;  // f[cur], g[cur] hold the current state
     double *rho = nullptr, *mux = nullptr, *mu = nullptr, *fy = nullptr;
     double *prev = nullptr, *obs = nullptr, *partial = nullptr, *red = nullptr;
     int red_blocks = 1;
@@ -45,7 +46,7 @@ constexpr int kDefaultChunk = 4;          // column nodes per thread before tuni
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t f, field, partial, red, total;
+    size_t f, g, field, partial, red, total;
 };
 
 Layout layout_for(const lbm_params *p, int red_blocks)
@@ -53,11 +54,13 @@ Layout layout_for(const lbm_params *p, int red_blocks)
     Layout L;
     const size_t N = (size_t)p->nx * p->ny;
     L.f = align256(9 * N * sizeof(double));
+    L.g = align256(3 * N * sizeof(double));
     L.field = align256(N * sizeof(double));
     L.partial = align256(2 * (size_t)red_blocks * sizeof(double));
     L.red = align256(2 * sizeof(double));
-    // f A/B, rho, mux, mu, fy, prev, 3 observation planes, partials, result
-    L.total = 2 * L.f + 8 * L.field + L.partial + L.red;
+    // f A/B, g A/B, rho, mux, mu, fy, prev, 3 observation planes, partials,
+    // result
+    L.total = 2 * L.f + 2 * L.g + 8 * L.field + L.partial + L.red;
     return L;
 }
 
@@ -209,6 +212,10 @@ void carve(lbm_ctx *c, int red_blocks)
     m += L.f;
     c->f[1] = (double *)m;
     m += L.f;
+    c->g[0] = (double *)m;
+    m += L.g;
+    c->g[1] = (double *)m;
+    m += L.g;
     double **fields[] = {&c->rho, &c->mux, &c->mu, &c->fy, &c->prev};
     for (double **q : fields) {
         *q = (double *)m;
@@ -226,9 +233,9 @@ lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
     for (int64_t s = 0; s < n; ++s) {
         const double *fc = c->f[c->cur];
         double *fn = c->f[1 - c->cur];
-        HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream));
+        HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, c->stream));
         HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
-        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream));
+        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->stream));
         c->cur = 1 - c->cur;
         c->steps += 1;
     }
@@ -239,7 +246,7 @@ lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
 lbm_status enqueue_fields(lbm_ctx *c)
 {
     const double *fc = c->f[c->cur];
-    HIP_OR(c, launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream));
+    HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, c->stream));
     HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
     return LBM_OK;
 }
@@ -382,6 +389,7 @@ lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, 
         }
     }
     if (e == hipSuccess) e = launch_init_feq(kp, d_rho, d_ux, d_uy, c->f[0], c->stream);
+    if (e == hipSuccess) e = launch_density_groups(kp, c->f[0], c->g[0], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string m = std::string("initialisation on the device failed: ") + hipGetErrorString(e);
@@ -489,6 +497,7 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int src_on_device)
     HIP_OR(c, hipMemcpyAsync(c->f[c->cur], f, 9 * c->N * sizeof(double),
                              src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                              c->stream));
+    HIP_OR(c, launch_density_groups(c->kp, c->f[c->cur], c->g[c->cur], c->stream));
     HIP_OR(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -513,6 +522,7 @@ lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int 
         HIP_OR(c, hipMemsetAsync(uy, 0, N * sizeof(double), c->stream));
     HIP_OR(c, launch_bare_velocity(c->kp, c->rho, fx, c->fy, ux, uy, c->stream));
     HIP_OR(c, launch_init_feq(c->kp, c->rho, ux, uy, c->f[c->cur], c->stream));
+    HIP_OR(c, launch_density_groups(c->kp, c->f[c->cur], c->g[c->cur], c->stream));
     HIP_OR(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -524,22 +534,22 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
     if (nsteps <= 0 || !ms_per_pass) return fail(c, LBM_E_INVALID, "nsteps > 0 and an output required");
     // Each pass is idempotent on the state: passes A and B rewrite the same
     // scalar planes from the same inputs and pass C writes only the spare
-    // distribution buffer.  So each is timed over nsteps back-to-back launches
+    // state buffers.  So each is timed over nsteps back-to-back launches
     // between two events, which keeps per-launch event overhead out of the
     // average.
     hipEvent_t e0, e1;
     HIP_OR(c, hipEventCreate(&e0));
     HIP_OR(c, hipEventCreate(&e1));
-    const double *fc = c->f[c->cur];
-    double *fn = c->f[1 - c->cur];
-    hipError_t err = launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream);
+    const double *fc = c->f[c->cur], *gc = c->g[c->cur];
+    double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
+    hipError_t err = launch_rows_rho(c->kp, fc, gc, c->rho, c->mux, c->stream);
     if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
     for (int q = 0; q < 3 && err == hipSuccess; ++q) {
         err = hipEventRecord(e0, c->stream);
         for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
-            if (q == 0) err = launch_rows_rho(c->kp, fc, c->rho, c->mux, c->stream);
+            if (q == 0) err = launch_rows_rho(c->kp, fc, gc, c->rho, c->mux, c->stream);
             if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
-            if (q == 2) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->stream);
+            if (q == 2) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->stream);
         }
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -562,7 +572,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     if (repeats <= 0) return fail(c, LBM_E_INVALID, "repeats must be positive");
     // the column pass reads rho and d2/dx2 rho and writes mu and F_y only,
     // so timing it repeatedly leaves the state untouched
-    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->rho, c->mux, c->stream));
+    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->g[c->cur], c->rho, c->mux, c->stream));
     hipEvent_t e0, e1;
     HIP_OR(c, hipEventCreate(&e0));
     HIP_OR(c, hipEventCreate(&e1));
@@ -600,8 +610,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     }
     if (err == hipSuccess) set_col_shape(&c->kp, best_w, best_c);
     // collision pass: populations held in registers or read twice.  It reads
-    // the current f, mu and F_y and writes only the spare buffer, so the state
-    // is untouched; mu and F_y are refreshed first with the chosen shape.
+    // the current f, mu and F_y and writes only the spare buffers, so the
+    // state is untouched; mu and F_y are refreshed first with the chosen shape.
     if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
     double best_row = INFINITY;
     int best_keep = c->kp.row_keep;
@@ -609,11 +619,11 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         KParams kp = c->kp;
         kp.row_keep = keep;
         const double *fc = c->f[c->cur];
-        double *fn = c->f[1 - c->cur];
-        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, c->stream);
+        double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
+        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
         for (int r = 0; r < repeats && err == hipSuccess; ++r)
-            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, c->stream);
+            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float t = 0.f;
@@ -718,7 +728,7 @@ struct lbm_batch {
     std::vector<lbm_status> status;
     int parity = 0;  // every active simulation holds its state in f[parity]
     int col_elems = 4096, col_lc = 8;
-    size_t row_lds = 0;
+    size_t row_lds = 0, rho_lds = 0;  // LDS of the collision pass and of pass A
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int64_t graph_len = 0;
     std::string err;
@@ -801,7 +811,7 @@ hipError_t batch_enqueue(lbm_batch *b, int64_t nsteps)
 {
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
-        e = launch_batch_rows_rho(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity, b->row_lds,
+        e = launch_batch_rows_rho(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity, b->rho_lds,
                                   b->stream);
         if (e == hipSuccess)
             e = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems,
@@ -893,7 +903,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
     if (hipGetDevice(&b->device) != hipSuccess) return give_up(LBM_E_DEVICE, "no HIP device");
     if (hipStreamCreate(&b->stream) != hipSuccess) return give_up(LBM_E_DEVICE, "hipStreamCreate");
 
-    // one allocation: per simulation f A/B, rho, mux, mu, fy, prev, partials
+    // one allocation: per simulation f A/B, g A/B, rho, mux, mu, fy, prev,
+    // partials
     size_t total = 0;
     std::vector<size_t> off(nsims);
     b->N.resize(nsims);
@@ -903,7 +914,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         b->N[s] = N;
         b->red_blocks[s] = rho_delta_blocks(b->kp[s]);
         off[s] = total;
-        total += 2 * align256(9 * N * sizeof(double)) + 5 * align256(N * sizeof(double)) +
+        total += 2 * align256(9 * N * sizeof(double)) + 2 * align256(3 * N * sizeof(double)) +
+                 5 * align256(N * sizeof(double)) +
                  align256(2 * (size_t)b->red_blocks[s] * sizeof(double));
     }
     if (hipMalloc(&b->mem, total) != hipSuccess) return give_up(LBM_E_NOMEM, "hipMalloc failed");
@@ -919,6 +931,10 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         m += align256(9 * N * sizeof(double));
         q.f[1] = (double *)m;
         m += align256(9 * N * sizeof(double));
+        for (int h = 0; h < 2; ++h) {
+            q.g[h] = (double *)m;
+            m += align256(3 * N * sizeof(double));
+        }
         double **planes[] = {&q.rho, &q.mux, &q.mu, &q.fy, &b->prev[s]};
         for (double **pl : planes) {
             *pl = (double *)m;
@@ -928,7 +944,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         rows_cap += (params[s].ny + b->kp[s].rows_per_block - 1) / b->kp[s].rows_per_block;
         cols_cap += params[s].nx;  // at most one column per workgroup
         const size_t re = (size_t)b->kp[s].rows_per_block * params[s].nx;
-        b->row_lds = std::max(b->row_lds, batch_row_lds((int)re));
+        b->row_lds = std::max(b->row_lds, batch_row_lds((int)re, true));
+        b->rho_lds = std::max(b->rho_lds, batch_row_lds((int)re, false));
     }
     if (hipMalloc(&b->d_kp, sizeof(KParams) * nsims) != hipSuccess ||
         hipMalloc(&b->d_sb, sizeof(SimBuffers) * nsims) != hipSuccess ||
@@ -954,6 +971,7 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
             duy = q.mu;
         }
         if (e == hipSuccess) e = launch_init_feq(b->kp[s], q.rho, dux, duy, q.f[0], b->stream);
+        if (e == hipSuccess) e = launch_density_groups(b->kp[s], q.f[0], q.g[0], b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess)
             return give_up(LBM_E_DEVICE, std::string("initialisation: ") + hipGetErrorString(e));
@@ -987,7 +1005,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int repeats, int *col_elems, int *ch
     if (repeats <= 0) return bfail(b, LBM_E_INVALID, "repeats must be positive");
     // the column pass writes mu and F_y only: the state is untouched
     BHIP_OR(b, launch_batch_rows_rho(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity,
-                                     b->row_lds, b->stream));
+                                     b->rho_lds, b->stream));
     hipEvent_t e0, e1;
     BHIP_OR(b, hipEventCreate(&e0));
     BHIP_OR(b, hipEventCreate(&e1));
@@ -1125,8 +1143,8 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx,
     const size_t N = b->N[sim];
     double *obs = nullptr;
     BHIP_OR(b, hipMalloc(&obs, 3 * N * sizeof(double)));
-    const double *fc = q.f[sim_parity(b, sim)];
-    hipError_t e = launch_rows_rho(k, fc, q.rho, q.mux, b->stream);
+    const double *fc = q.f[sim_parity(b, sim)], *gc = q.g[sim_parity(b, sim)];
+    hipError_t e = launch_rows_rho(k, fc, gc, q.rho, q.mux, b->stream);
     if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
         e = launch_rows_observe(k, fc, q.mu, q.fy, obs, obs + N, obs + 2 * N, nullptr, b->stream);
@@ -1165,8 +1183,8 @@ lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, c
     BHIP_OR(b, hipStreamSynchronize(b->stream));
     BHIP_OR(b, hipMalloc(&tmp, 3 * N * sizeof(double)));
     double *fx = tmp, *ux = tmp + N, *uy = tmp + 2 * N;
-    double *fc = q.f[sim_parity(b, sim)];
-    hipError_t e = launch_rows_rho(k, fc, q.rho, q.mux, b->stream);
+    double *fc = q.f[sim_parity(b, sim)], *gc = q.g[sim_parity(b, sim)];
+    hipError_t e = launch_rows_rho(k, fc, gc, q.rho, q.mux, b->stream);
     if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
         e = launch_rows_observe(k, fc, q.mu, q.fy, nullptr, nullptr, nullptr, fx, b->stream);
@@ -1178,6 +1196,7 @@ lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, c
                : hipMemsetAsync(uy, 0, N * sizeof(double), b->stream);
     if (e == hipSuccess) e = launch_bare_velocity(k, q.rho, fx, q.fy, ux, uy, b->stream);
     if (e == hipSuccess) e = launch_init_feq(k, q.rho, ux, uy, fc, b->stream);
+    if (e == hipSuccess) e = launch_density_groups(k, fc, gc, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     (void)hipFree(tmp);
     if (e != hipSuccess)

@@ -331,6 +331,18 @@ __global__ void k_init_feq(KParams p, const double *__restrict__ rho0,
     }
 }
 
+// The three density groups of a state f, in the order the collision pass
+// sums them: g0 = (f0 + f1) + f3, g1 = (f2 + f5) + f6, g2 = (f4 + f7) + f8.
+__global__ void k_density_groups(size_t N, const double *__restrict__ f, double *__restrict__ g)
+{
+    for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+        g[n] = (f[n] + f[N + n]) + f[3 * N + n];
+        g[N + n] = (f[2 * N + n] + f[5 * N + n]) + f[6 * N + n];
+        g[2 * N + n] = (f[4 * N + n] + f[7 * N + n]) + f[8 * N + n];
+    }
+}
+
 constexpr int kRedThreads = 256;
 
 __global__ __launch_bounds__(kRedThreads) void k_rho_delta(KParams p, const double *__restrict__ f,
@@ -463,10 +475,10 @@ static bool col_fast(const KParams &p) { return p.ny >= kFastMinLine; }
             hipLaunchKernelGGL((K<false, 1024 __VA_OPT__(,) __VA_ARGS__>), GRID);\
     } while (0)
 
-hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *mux,
-                           hipStream_t s)
+hipError_t launch_rows_rho(const KParams &p, const double *f, const double *g, double *rho,
+                           double *mux, hipStream_t s)
 {
-    if (p.use_iir_rows) return launch_rows_rho_iir(p, f, rho, mux, s);
+    if (p.use_iir_rows) return launch_rows_rho_iir(p, g, rho, mux, s);
 #define GRID dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, rho, mux
     CPLBM_DISPATCH(k_rows_rho, row_fast(p), p.row_threads);
 #undef GRID
@@ -484,11 +496,11 @@ hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux
 }
 
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *fout, hipStream_t s)
+                               const double *fy, double *fout, double *gout, hipStream_t s)
 {
     if (p.use_iir_rows)
-        return launch_rows_collide_iir(p, f, mu, fy, fout, nullptr, nullptr, nullptr, nullptr,
-                                       false, s);
+        return launch_rows_collide_iir(p, f, mu, fy, fout, gout, nullptr, nullptr, nullptr,
+                                       nullptr, false, s);
 #define GRID                                                                                 \
     dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, mu, fy, fout, nullptr,    \
         nullptr, nullptr, nullptr
@@ -502,7 +514,7 @@ hipError_t launch_rows_observe(const KParams &p, const double *f, const double *
                                double *fx, hipStream_t s)
 {
     if (p.use_iir_rows)
-        return launch_rows_collide_iir(p, f, mu, fy, nullptr, rho, vx, vy, fx, true, s);
+        return launch_rows_collide_iir(p, f, mu, fy, nullptr, nullptr, rho, vx, vy, fx, true, s);
 #define GRID                                                                                 \
     dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, mu, fy, nullptr, rho, vx, \
         vy, fx
@@ -542,6 +554,15 @@ hipError_t launch_init_feq(const KParams &p, const double *rho0, const double *u
     int blocks = (int)((N + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_init_feq, dim3(blocks), dim3(256), 0, s, p, rho0, ux0, uy0, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_groups(const KParams &p, const double *f, double *g, hipStream_t s)
+{
+    const size_t N = (size_t)p.nx * p.ny;
+    int blocks = (int)((N + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_density_groups, dim3(blocks), dim3(256), 0, s, N, f, g);
     return hipGetLastError();
 }
 

@@ -41,21 +41,30 @@ constexpr int kIirRowChunk = 4;
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
 
-// Pass A over rows: rho = sum f and the row part of the chemical potential
-// (Eq. 33), mux = k^2 psi'(rho) - kappa d2rho/dx2 (k^2 psi'(rho) when kappa = 0).
-hipError_t launch_rows_rho(const KParams &p, const double *f, double *rho, double *mux,
-                           hipStream_t s);
+// The state is f together with its three density groups g (3 planes of N):
+// at each node g0 = (f0 + f1) + f3, g1 = (f2 + f5) + f6, g2 = (f4 + f7) + f8,
+// so that rho = (g0 + g1) + g2.  The collision pass writes g with the new f;
+// wherever f is set otherwise, launch_density_groups forms them.
+//
+// Pass A over rows: rho and the row part of the chemical potential (Eq. 33),
+// mux = k^2 psi'(rho) - kappa d2rho/dx2 (k^2 psi'(rho) when kappa = 0).  The
+// fast kernels read rho from g, the general ones sum f.
+hipError_t launch_rows_rho(const KParams &p, const double *f, const double *g, double *rho,
+                           double *mux, hipStream_t s);
 // Pass B over columns: d/dy rho, d2/dy2 rho, mu = mux - kappa d2rho/dy2 (Eq. 33),
 // d/dy mu, F_y (Eq. 12).
 hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux, double *mu,
                           double *fy, hipStream_t s);
-// Pass C over rows: d/dx rho, d/dx mu, F_x, collision and streaming f -> fout.
+// Pass C over rows: d/dx rho, d/dx mu, F_x, collision and streaming f -> fout,
+// and (fast kernels) the density groups gout of fout.
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *fout, hipStream_t s);
+                               const double *fy, double *fout, double *gout, hipStream_t s);
 // Pass C in observation mode: rho, v = u + F/(2 rho), F_x (any output may be null).
 hipError_t launch_rows_observe(const KParams &p, const double *f, const double *mu,
                                const double *fy, double *rho, double *vx, double *vy,
                                double *fx, hipStream_t s);
+// g = the density groups of f.
+hipError_t launch_density_groups(const KParams &p, const double *f, double *g, hipStream_t s);
 // f = feq(rho0, u0) (u0 pointers may be null: rest).
 hipError_t launch_init_feq(const KParams &p, const double *rho0, const double *ux0,
                            const double *uy0, double *f, hipStream_t s);
@@ -79,16 +88,17 @@ void set_col_shape(KParams *p, int width, int chunk);
 // ---- batches of independent meshes ------------------------------------
 // Device-side buffers of one mesh of a batch.
 struct SimBuffers {
-    double *f[2];
+    double *f[2], *g[2];  // state A/B: distribution and its density groups
     double *rho, *mux, *mu, *fy;
 };
 // One workgroup of a batched pass: the mesh and its first row or column.
 struct WorkItem {
     int sim, start;
 };
-// LDS of a batched row block holding rows_elems nodes, and of a batched
-// column block of col_elems nodes in chunks of lc.
-size_t batch_row_lds(int rows_elems);
+// LDS of a batched row block holding rows_elems nodes (pass A, or the
+// collision pass), and of a batched column block of col_elems nodes in
+// chunks of lc.
+size_t batch_row_lds(int rows_elems, bool collide);
 size_t batch_col_lds(int col_elems, int lc);
 // Batched passes: rows use 256-thread workgroups (each mesh's rows_per_block
 // rows of nx <= 1024 nodes); the column pass uses col_elems / lc threads
@@ -104,12 +114,13 @@ hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
 // Fast-path kernels (kernels_iir.hip) and their eligibility.
 bool iir_rows_ok(const KParams &p);
 bool iir_cols_ok(const KParams &p, int chunk, int width);
-hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *mux,
+hipError_t launch_rows_rho_iir(const KParams &p, const double *g, double *rho, double *mux,
                                hipStream_t s);
 hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
                               double *fy, hipStream_t s);
 hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,
-                                   const double *fy, double *fout, double *o_rho, double *o_vx,
-                                   double *o_vy, double *o_fx, bool observe, hipStream_t s);
+                                   const double *fy, double *fout, double *gout, double *o_rho,
+                                   double *o_vx, double *o_vy, double *o_fx, bool observe,
+                                   hipStream_t s);
 
 }  // namespace cplbm

@@ -160,7 +160,9 @@ constexpr int kRowLC = 4;
 
 // Pass A on rows [y0, y0 + rows_per_block) of one mesh: rho, and the row part
 // of the chemical potential of Eq. 33, k^2 psi'(rho) - kappa d2rho/dx2.
-__device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const double *__restrict__ f,
+// rho comes from the state's three density groups g (written by the previous
+// collision pass): rho = (g0 + g1) + g2.
+__device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const double *__restrict__ g,
                                               double *__restrict__ rho_out,
                                               double *__restrict__ mux_out)
 {
@@ -174,17 +176,12 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     const size_t base = (size_t)(y0 + m.l) * nx + m.c * LC;
     double rho[LC];
     if (m.ok) {
-        double acc[LC];
-        vload<LC>(f + base, acc);
+        double g0[LC], g1[LC], g2[LC];
+        vload<LC>(g + base, g0);
+        vload<LC>(g + N + base, g1);
+        vload<LC>(g + 2 * N + base, g2);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            double t[LC];
-            vload<LC>(f + i * N + base, t);
-#pragma unroll
-            for (int k = 0; k < LC; ++k) acc[k] += t[k];
-        }
-#pragma unroll
-        for (int k = 0; k < LC; ++k) rho[k] = acc[k];
+        for (int k = 0; k < LC; ++k) rho[k] = (g0[k] + g1[k]) + g2[k];
         vstore<LC>(rho_out + base, rho);
     }
     // bulk part first: its transcendental work overlaps the solves' barriers
@@ -208,11 +205,11 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
 }
 
 template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ f,
+__global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ g,
                                                        double *__restrict__ rho_out,
                                                        double *__restrict__ mux_out)
 {
-    rows_rho_body(p, blockIdx.x * p.rows_per_block, f, rho_out, mux_out);
+    rows_rho_body(p, blockIdx.x * p.rows_per_block, g, rho_out, mux_out);
 }
 
 __device__ __forceinline__ int strip_of_block(const KParams &p)
@@ -287,11 +284,21 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
 // KEEP: the nine populations stay in registers from the first read to the
 // collision; otherwise each is read again when needed (fewer registers, so
 // more waves per SIMD; the second read is served by the caches).
+//
+// Besides the new state fout, the pass writes its three density groups gout
+// (planes of N): with f the streamed populations at a node,
+//   g0 = (f0 + f1) + f3,   g1 = (f2 + f5) + f6,   g2 = (f4 + f7) + f8,
+// the populations that arrive from the same row, from the row below and from
+// the row above.  The next pass A forms rho = (g0 + g1) + g2 from them and so
+// reads 3 planes instead of 9.  Each group is summed in this order whatever
+// the source of its members (shifted along the row, or bounced back at a
+// wall), so the groups are a function of fout alone.
 template <bool OBSERVE, bool KEEP>
 __device__ __forceinline__ void rows_collide_body(
     const KParams &p, int y0, const double *__restrict__ f, const double *__restrict__ mu,
-    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
-    double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
+    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
+    double *__restrict__ o_rho, double *__restrict__ o_vx, double *__restrict__ o_vy,
+    double *__restrict__ o_fx)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
@@ -299,7 +306,8 @@ __device__ __forceinline__ void rows_collide_body(
     const size_t N = (size_t)nx * ny;
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
-    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
+    const int nlc = p.rows_per_block * m.nc;
+    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + nlc;
     const int y = y0 + m.l, x0 = m.c * LC;
     const size_t base = (size_t)y * nx + x0;
     constexpr int NI = KEEP ? 9 : 1;
@@ -338,126 +346,241 @@ __device__ __forceinline__ void rows_collide_body(
     double dxr[LC], dxm[LC];
     iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, dxr);
     iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, mv, 1.0, vbuf, cP, cB, dxm);
-    if (!m.ok) return;
-    double Fy[LC];
-    vload<LC>(fy + base, Fy);
-    double ux[LC], uy[LC], vx2[LC], vy2[LC], uu[LC], uu2[LC];
+    double Fy[LC], Fx[LC];
+    if (m.ok) {
+        vload<LC>(fy + base, Fy);
 #pragma unroll
-    for (int k = 0; k < LC; ++k) {
-        const double rh = rho[k], ir = 1.0 / rh;
-        const double Fx = -rh * dxm[k] + CS2 * dxr[k];
-        ux[k] = jx[k] * ir;
-        uy[k] = jy[k] * ir;
-        if (OBSERVE) {
-            const size_t node = base + k;
-            if (o_rho) o_rho[node] = rh;
-            if (o_vx) o_vx[node] = ux[k] + 0.5 * Fx * ir;
-            if (o_vy) o_vy[node] = uy[k] + 0.5 * Fy[k] * ir;
-            if (o_fx) o_fx[node] = Fx;
-            continue;
-        }
-        vx2[k] = ux[k] + Fx * ir;
-        vy2[k] = uy[k] + Fy[k] * ir;
-        uu[k] = ux[k] * ux[k] + uy[k] * uy[k];
-        uu2[k] = vx2[k] * vx2[k] + vy2[k] * vy2[k];
+        for (int k = 0; k < LC; ++k) Fx[k] = -rho[k] * dxm[k] + CS2 * dxr[k];
     }
-    if (OBSERVE) return;
-    // collision and push streaming, one population at a time: population i
-    // of node (x, y) goes to (x + e_x, y + e_y)
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        double q[LC], v[LC];
-        if (KEEP) {
-#pragma unroll
-            for (int k = 0; k < LC; ++k) q[k] = fi[KEEP ? i : 0][k];
-        } else {
-            vload<LC>(f + i * N + base, q);
-        }
+    if (OBSERVE) {
+        if (!m.ok) return;
 #pragma unroll
         for (int k = 0; k < LC; ++k) {
-            const double eq = feq(i, rho[k], ux[k], uy[k], uu[k]);
-            const double eq2 = feq(i, rho[k], vx2[k], vy2[k], uu2[k]);
-            v[k] = q[k] - (q[k] - eq) * p.inv_tau + (eq2 - eq);
+            const double rh = rho[k], ir = 1.0 / rh;
+            const double ux = jx[k] * ir, uy = jy[k] * ir;
+            const size_t node = base + k;
+            if (o_rho) o_rho[node] = rh;
+            if (o_vx) o_vx[node] = ux + 0.5 * Fx[k] * ir;
+            if (o_vy) o_vy[node] = uy + 0.5 * Fy[k] * ir;
+            if (o_fx) o_fx[node] = Fx[k];
         }
-        int ty = y + EY[i];
-        if (ty < 0 || ty >= ny) {
-            if (p.bc_y) {
+        return;
+    }
+    // Edge exchange of the density groups: the value a chunk's first node
+    // receives from the left neighbour (populations 1, 5, 8) and its last
+    // node from the right neighbour (3, 6, 7), six slots per chunk.
+    double *edge = cB + nlc;
+    const int slot = m.l * m.nc + m.c;
+    // the row's down-going groups bounce back at a bottom wall, the
+    // up-going ones at a top wall
+    const bool refl_d = p.bc_y && y == 0, refl_u = p.bc_y && y == ny - 1;
+    double gm[LC], gu[LC], gd[LC], hm = 0.0, hu = 0.0, hd = 0.0;
+    if (m.ok) {
+        double ux[LC], uy[LC], vx2[LC], vy2[LC], uu[LC], uu2[LC];
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            const double ir = 1.0 / rho[k];
+            ux[k] = jx[k] * ir;
+            uy[k] = jy[k] * ir;
+            vx2[k] = ux[k] + Fx[k] * ir;
+            vy2[k] = uy[k] + Fy[k] * ir;
+            uu[k] = ux[k] * ux[k] + uy[k] * uy[k];
+            uu2[k] = vx2[k] * vx2[k] + vy2[k] * vy2[k];
+        }
+        // collision and push streaming, one population at a time: population
+        // i of node (x, y) goes to (x + e_x, y + e_y)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            double q[LC], v[LC];
+            if (KEEP) {
+#pragma unroll
+                for (int k = 0; k < LC; ++k) q[k] = fi[KEEP ? i : 0][k];
+            } else {
+                vload<LC>(f + i * N + base, q);
+            }
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                const double eq = feq(i, rho[k], ux[k], uy[k], uu[k]);
+                const double eq2 = feq(i, rho[k], vx2[k], vy2[k], uu2[k]);
+                v[k] = q[k] - (q[k] - eq) * p.inv_tau + (eq2 - eq);
+            }
+            const bool refl = (EY[i] < 0 && refl_d) || (EY[i] > 0 && refl_u);
+            if (refl) {
                 // half-way bounce-back into the opposite population of the
                 // same node; a moving wall adds -2 w rho (e.U)/c_s^2
 #pragma unroll
                 for (int k = 0; k < LC; ++k)
                     v[k] = v[k] - 2.0 * WT[i] * rho[k] * (EX[i] * p.wall_ux) / CS2;
+            }
+            // density groups at the arrival nodes; a value that arrives
+            // from a neighbouring chunk is added after the exchange, and a
+            // later member that must follow it waits in hm, hu or hd
+            switch (i) {
+            case 0:
+#pragma unroll
+                for (int k = 0; k < LC; ++k) gm[k] = v[k];
+                break;
+            case 1:
+#pragma unroll
+                for (int k = 1; k < LC; ++k) gm[k] += v[k - 1];
+                edge[0 * nlc + slot] = v[LC - 1];
+                break;
+            case 3:
+#pragma unroll
+                for (int k = 1; k < LC - 1; ++k) gm[k] += v[k + 1];
+                hm = v[1];
+                edge[1 * nlc + slot] = v[0];
+                break;
+            case 2:
+#pragma unroll
+                for (int k = 0; k < LC; ++k) gu[k] = v[k];
+                break;
+            case 5:
+                if (refl_u) {
+#pragma unroll
+                    for (int k = 0; k < LC; ++k) gu[k] += v[k];
+                } else {
+#pragma unroll
+                    for (int k = 1; k < LC; ++k) gu[k] += v[k - 1];
+                    edge[2 * nlc + slot] = v[LC - 1];
+                }
+                break;
+            case 6:
+                if (refl_u) {
+#pragma unroll
+                    for (int k = 0; k < LC; ++k) gu[k] += v[k];
+                } else {
+#pragma unroll
+                    for (int k = 1; k < LC - 1; ++k) gu[k] += v[k + 1];
+                    hu = v[1];
+                    edge[3 * nlc + slot] = v[0];
+                }
+                break;
+            case 4:
+#pragma unroll
+                for (int k = 0; k < LC; ++k) gd[k] = v[k];
+                break;
+            case 7:
+                if (refl_d) {
+#pragma unroll
+                    for (int k = 0; k < LC; ++k) gd[k] += v[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < LC - 1; ++k) gd[k] += v[k + 1];
+                    edge[4 * nlc + slot] = v[0];
+                }
+                break;
+            case 8:
+                if (refl_d) {
+#pragma unroll
+                    for (int k = 0; k < LC; ++k) gd[k] += v[k];
+                } else {
+#pragma unroll
+                    for (int k = 1; k < LC - 1; ++k) gd[k] += v[k - 1];
+                    hd = v[LC - 2];
+                    edge[5 * nlc + slot] = v[LC - 1];
+                }
+                break;
+            default: break;
+            }
+            if (refl) {
                 vstore<LC>(fout + OPP[i] * N + base, v);
                 continue;
             }
-            ty = ty < 0 ? ty + ny : ty - ny;
-        }
-        double *dst = fout + i * N + (size_t)ty * nx;
-        if (EX[i] == 0) {
-            vstore<LC>(dst + x0, v);
-            continue;
-        }
-        // Shifted populations: the aligned chunk [x0, x0 + LC) of the target
-        // row receives LC - 1 of this thread's values and one value of the
-        // neighbouring chunk, taken from the adjacent lane.  Where that chunk
-        // is not on the adjacent lane (first/last lane of the wave, first/last
-        // chunk of the row), the boundary value goes out as a single store
-        // from its owner instead.
-        const int lane = threadIdx.x & 63;
-        if (EX[i] > 0) {
-            const double from_left = __shfl_up(v[LC - 1], 1);
-            const bool left_here = lane > 0 && m.c > 0;
-            double w[LC];
-            w[0] = from_left;
+            int ty = y + EY[i];
+            ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
+            double *dst = fout + i * N + (size_t)ty * nx;
+            if (EX[i] == 0) {
+                vstore<LC>(dst + x0, v);
+                continue;
+            }
+            // Shifted populations: the aligned chunk [x0, x0 + LC) of the
+            // target row receives LC - 1 of this thread's values and one
+            // value of the neighbouring chunk, taken from the adjacent lane.
+            // Where that chunk is not on the adjacent lane (first/last lane
+            // of the wave, first/last chunk of the row), the boundary value
+            // goes out as a single store from its owner instead.
+            const int lane = threadIdx.x & 63;
+            if (EX[i] > 0) {
+                const double from_left = __shfl_up(v[LC - 1], 1);
+                const bool left_here = lane > 0 && m.c > 0;
+                double w[LC];
+                w[0] = from_left;
 #pragma unroll
-            for (int k = 1; k < LC; ++k) w[k] = v[k - 1];
-            if (left_here) {
-                vstore<LC>(dst + x0, w);
+                for (int k = 1; k < LC; ++k) w[k] = v[k - 1];
+                if (left_here) {
+                    vstore<LC>(dst + x0, w);
+                } else {
+#pragma unroll
+                    for (int k = 1; k < LC; ++k) dst[x0 + k] = w[k];
+                }
+                const bool right_here = lane < 63 && m.c < m.nc - 1;
+                if (!right_here) {
+                    const int tx = x0 + LC == nx ? 0 : x0 + LC;
+                    dst[tx] = v[LC - 1];
+                }
             } else {
+                const double from_right = __shfl_down(v[0], 1);
+                const bool right_here = lane < 63 && m.c < m.nc - 1;
+                double w[LC];
 #pragma unroll
-                for (int k = 1; k < LC; ++k) dst[x0 + k] = w[k];
-            }
-            const bool right_here = lane < 63 && m.c < m.nc - 1;
-            if (!right_here) {
-                const int tx = x0 + LC == nx ? 0 : x0 + LC;
-                dst[tx] = v[LC - 1];
-            }
-        } else {
-            const double from_right = __shfl_down(v[0], 1);
-            const bool right_here = lane < 63 && m.c < m.nc - 1;
-            double w[LC];
+                for (int k = 0; k < LC - 1; ++k) w[k] = v[k + 1];
+                w[LC - 1] = from_right;
+                if (right_here) {
+                    vstore<LC>(dst + x0, w);
+                } else {
 #pragma unroll
-            for (int k = 0; k < LC - 1; ++k) w[k] = v[k + 1];
-            w[LC - 1] = from_right;
-            if (right_here) {
-                vstore<LC>(dst + x0, w);
-            } else {
-#pragma unroll
-                for (int k = 0; k < LC - 1; ++k) dst[x0 + k] = w[k];
-            }
-            const bool left_here = lane > 0 && m.c > 0;
-            if (!left_here) {
-                const int tx = x0 == 0 ? nx - 1 : x0 - 1;
-                dst[tx] = v[0];
+                    for (int k = 0; k < LC - 1; ++k) dst[x0 + k] = w[k];
+                }
+                const bool left_here = lane > 0 && m.c > 0;
+                if (!left_here) {
+                    const int tx = x0 == 0 ? nx - 1 : x0 - 1;
+                    dst[tx] = v[0];
+                }
             }
         }
     }
+    __syncthreads();
+    if (!m.ok) return;
+    // x is periodic: the neighbours of the first and last chunk wrap
+    const int row0 = m.l * m.nc;
+    const int left = row0 + (m.c > 0 ? m.c - 1 : m.nc - 1);
+    const int right = row0 + (m.c < m.nc - 1 ? m.c + 1 : 0);
+    gm[0] = (gm[0] + edge[0 * nlc + left]) + hm;
+    gm[LC - 1] += edge[1 * nlc + right];
+    if (!refl_u) {
+        gu[0] = (gu[0] + edge[2 * nlc + left]) + hu;
+        gu[LC - 1] += edge[3 * nlc + right];
+    }
+    if (!refl_d) {
+        gd[0] += edge[5 * nlc + left];
+        gd[LC - 1] = (gd[LC - 1] + edge[4 * nlc + right]) + hd;
+    }
+    // g0 of this row; g1 of the row above (of this row at a top wall, as
+    // g2); g2 of the row below (of this row at a bottom wall, as g1)
+    vstore<LC>(gout + base, gm);
+    const size_t up = refl_u ? 2 * N + base : N + (size_t)(y + 1 < ny ? y + 1 : 0) * nx + x0;
+    const size_t dn = refl_d ? N + base : 2 * N + (size_t)(y > 0 ? y - 1 : ny - 1) * nx + x0;
+    vstore<LC>(gout + up, gu);
+    vstore<LC>(gout + dn, gd);
 }
 
 template <int MAXT, bool OBSERVE, bool KEEP>
 __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     KParams p, const double *__restrict__ f, const double *__restrict__ mu,
-    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ o_rho,
-    double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
+    const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
+    double *__restrict__ o_rho, double *__restrict__ o_vx, double *__restrict__ o_vy,
+    double *__restrict__ o_fx)
 {
-    rows_collide_body<OBSERVE, KEEP>(p, blockIdx.x * p.rows_per_block, f, mu, fy, fout, o_rho,
-                                     o_vx, o_vy, o_fx);
+    rows_collide_body<OBSERVE, KEEP>(p, blockIdx.x * p.rows_per_block, f, mu, fy, fout, gout,
+                                     o_rho, o_vx, o_vy, o_fx);
 }
 
 // ---- batched passes: one launch covers the blocks of every active mesh ----
 // Work item b names the mesh and its first row (row passes) or column
 // (column pass); each mesh has its own parameter block and buffers.  parity
-// selects which of the mesh's two distribution buffers holds the state.
+// selects which of the mesh's two state buffers (distribution and density
+// groups) holds the state.
 
 __global__ __launch_bounds__(256) void kb_rows_rho(const KParams *__restrict__ kps,
                                                    const SimBuffers *__restrict__ sb,
@@ -465,7 +588,7 @@ __global__ __launch_bounds__(256) void kb_rows_rho(const KParams *__restrict__ k
 {
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
-    rows_rho_body(kps[w.sim], w.start, b.f[parity], b.rho, b.mux);
+    rows_rho_body(kps[w.sim], w.start, b.g[parity], b.rho, b.mux);
 }
 
 template <int LC, int MAXT>
@@ -486,14 +609,17 @@ __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
     rows_collide_body<false, true>(kps[w.sim], w.start, b.f[parity], b.mu, b.fy,
-                                   b.f[1 - parity], nullptr, nullptr, nullptr, nullptr);
+                                   b.f[1 - parity], b.g[1 - parity], nullptr, nullptr, nullptr,
+                                   nullptr);
 }
 
 }  // namespace
 
-size_t batch_row_lds(int rows_elems)
+// line values, the solve's two carry planes and (collision pass) six edge
+// planes, one slot per chunk each
+size_t batch_row_lds(int rows_elems, bool collide)
 {
-    return sizeof(double) * ((size_t)rows_elems + 2 * (size_t)rows_elems / kRowLC);
+    return sizeof(double) * ((size_t)rows_elems + (collide ? 8 : 2) * (size_t)rows_elems / kRowLC);
 }
 
 size_t batch_col_lds(int col_elems, int lc)
@@ -547,10 +673,9 @@ bool iir_cols_ok(const KParams &p, int lc, int width)
            width * p.ny <= kMaxBlockElems;
 }
 
-static size_t row_lds_iir(const KParams &p)
+static size_t row_lds_iir(const KParams &p, bool collide)
 {
-    const size_t R = p.rows_per_block;
-    return sizeof(double) * (R * p.nx + 2 * R * (p.nx / kRowLC));
+    return batch_row_lds(p.rows_per_block * p.nx, collide);
 }
 
 static size_t col_lds_iir(const KParams &p)
@@ -570,11 +695,11 @@ static int col_threads_iir(const KParams &p) { return p.cols_per_block * (p.ny /
             hipLaunchKernelGGL(K1024, GRIDARGS);                                           \
     } while (0)
 
-hipError_t launch_rows_rho_iir(const KParams &p, const double *f, double *rho, double *mux,
+hipError_t launch_rows_rho_iir(const KParams &p, const double *g, double *rho, double *mux,
                                hipStream_t s)
 {
     const int T = row_threads_iir(p);
-#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, rho, mux
+#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, g, rho, mux
     CPLBM_IIR_THREADS(T, k_rows_rho_iir<256>, k_rows_rho_iir<1024>, ARGS);
 #undef ARGS
     return hipGetLastError();
@@ -595,12 +720,14 @@ hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double 
 }
 
 hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,
-                                   const double *fy, double *fout, double *o_rho, double *o_vx,
-                                   double *o_vy, double *o_fx, bool observe, hipStream_t s)
+                                   const double *fy, double *fout, double *gout, double *o_rho,
+                                   double *o_vx, double *o_vy, double *o_fx, bool observe,
+                                   hipStream_t s)
 {
     const int T = row_threads_iir(p);
 #define ARGS                                                                                   \
-    dim3(row_blocks(p)), dim3(T), row_lds_iir(p), s, p, f, mu, fy, fout, o_rho, o_vx, o_vy, o_fx
+    dim3(row_blocks(p)), dim3(T), row_lds_iir(p, true), s, p, f, mu, fy, fout, gout, o_rho,     \
+        o_vx, o_vy, o_fx
     // holding f in registers only pays with 256-thread blocks (no spills)
     const bool keep = p.row_keep && T <= 256;
     if (observe)

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "lnx.hpp"
 
 namespace cplbm {
 namespace phys {
@@ -50,7 +51,7 @@ __device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
     switch (p.eos) {
     case 0: {  // van der Waals
         const double iv = 1.0 / (1.0 - br);
-        m = RT * (log(rho * iv) + iv) - 2.0 * p.a * rho;
+        m = RT * (lnx(rho * iv) + iv) - 2.0 * p.a * rho;
         break;
     }
     case 1:
@@ -59,7 +60,7 @@ __device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
         const double d1 = 1.0 - br, d2 = 1.0 + br;
         const double inv = 1.0 / (d1 * d2);
         const double iv = d2 * inv;
-        m = RT * log(rho * iv) + RT * iv - p.eos_c1 * log(d2) - A * rho * (d1 * inv);
+        m = RT * lnx(rho * iv) + RT * iv - p.eos_c1 * lnx(d2) - A * rho * (d1 * inv);
         break;
     }
     case 3: {  // Peng-Robinson; eos_c1 = A / (2 sqrt(2) b)
@@ -69,13 +70,13 @@ __device__ __forceinline__ double mu0_capped(const KParams &p, double rho)
         const double d1 = 1.0 - br, d2 = s2 + 1.0 - br, d3 = 1.0 + 2.0 * br - br * br;
         const double inv = 1.0 / (d1 * d2 * d3);
         const double iv = d2 * d3 * inv;
-        m = RT * log(rho * iv) - p.eos_c1 * log((s2 - 1.0 + br) * (d1 * d3 * inv)) + RT * iv -
+        m = RT * lnx(rho * iv) - p.eos_c1 * lnx((s2 - 1.0 + br) * (d1 * d3 * inv)) + RT * iv -
             A * rho * (d1 * d2 * inv);
         break;
     }
     default: {  // Carnahan-Starling
         const double eta = br * 0.25, q = 1.0 - eta;
-        m = RT * ((3.0 - eta) / (q * q * q) + log(rho) + 1.0) - 2.0 * p.a * rho;
+        m = RT * ((3.0 - eta) / (q * q * q) + lnx(rho) + 1.0) - 2.0 * p.a * rho;
         break;
     }
     }
