@@ -728,6 +728,7 @@ struct lbm_batch {
     std::vector<lbm_status> status;
     int parity = 0;  // every active simulation holds its state in f[parity]
     int col_elems = 4096, col_lc = 8;
+    int col_wmax = 1;  // widest strip (columns) of any simulation
     size_t row_lds = 0, rho_lds = 0;  // LDS of the collision pass and of pass A
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int64_t graph_len = 0;
@@ -768,13 +769,16 @@ void batch_drop_graphs(lbm_batch *b)
 bool batch_apply_col_shape(lbm_batch *b, int col_elems, int lc)
 {
     std::vector<KParams> kp = b->kp;
+    int wmax = 1;
     for (int s = 0; s < b->n; ++s) {
         set_col_shape(&kp[s], col_elems / kp[s].ny, lc);
         if (!kp[s].use_iir_cols || kp[s].cols_per_block * kp[s].ny > col_elems) return false;
+        wmax = std::max(wmax, kp[s].cols_per_block);
     }
     b->kp = kp;
     b->col_elems = col_elems;
     b->col_lc = lc;
+    b->col_wmax = wmax;
     return true;
 }
 
@@ -815,7 +819,7 @@ hipError_t batch_enqueue(lbm_batch *b, int64_t nsteps)
                                   b->stream);
         if (e == hipSuccess)
             e = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems,
-                                     b->col_lc, b->stream);
+                                     b->col_lc, b->col_wmax, b->stream);
         if (e == hipSuccess)
             e = launch_batch_rows_collide(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity,
                                           b->row_lds, b->stream);
@@ -943,9 +947,9 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         b->partial[s] = (double *)m;
         rows_cap += (params[s].ny + b->kp[s].rows_per_block - 1) / b->kp[s].rows_per_block;
         cols_cap += params[s].nx;  // at most one column per workgroup
-        const size_t re = (size_t)b->kp[s].rows_per_block * params[s].nx;
-        b->row_lds = std::max(b->row_lds, batch_row_lds((int)re, true));
-        b->rho_lds = std::max(b->rho_lds, batch_row_lds((int)re, false));
+        const int R = b->kp[s].rows_per_block, nx = params[s].nx;
+        b->row_lds = std::max(b->row_lds, batch_row_lds(R, nx, true));
+        b->rho_lds = std::max(b->rho_lds, batch_row_lds(R, nx, false));
     }
     if (hipMalloc(&b->d_kp, sizeof(KParams) * nsims) != hipSuccess ||
         hipMalloc(&b->d_sb, sizeof(SimBuffers) * nsims) != hipSuccess ||
@@ -1017,11 +1021,11 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int repeats, int *col_elems, int *ch
         if (!batch_apply_col_shape(b, cand[c][0], cand[c][1])) continue;
         if (batch_upload(b) != LBM_OK) break;
         err = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems, b->col_lc,
-                                   b->stream);
+                                   b->col_wmax, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
         for (int r = 0; r < repeats && err == hipSuccess; ++r)
             err = launch_batch_cols_mu(b->d_kp, b->d_sb, b->d_cols, b->n_cols, b->col_elems,
-                                       b->col_lc, b->stream);
+                                       b->col_lc, b->col_wmax, b->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float t = 0.f;

@@ -450,8 +450,8 @@ void set_col_shape(KParams *p, int width, int chunk)
     p->cols_per_block = w;
     p->col_threads = round_threads(w * p->ny);
     p->col_lc = chunk;
-    p->use_iir_cols = (chunk == 4 || chunk == 8 || chunk == 16) && iir_cols_ok(*p, chunk, w);
     iir_carry(*p, chunk, &p->iir_m_col, &p->iir_qL_col);
+    p->use_iir_cols = (chunk == 4 || chunk == 8 || chunk == 16) && iir_cols_ok(*p, chunk, w);
     const int nb = col_blocks(*p);
     p->col_xcd_groups = (nb % 8 == 0 && nb >= 64 && p->nx % w == 0) ? 8 : 1;
 }

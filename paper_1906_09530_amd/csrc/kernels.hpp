@@ -95,18 +95,18 @@ struct SimBuffers {
 struct WorkItem {
     int sim, start;
 };
-// LDS of a batched row block holding rows_elems nodes (pass A, or the
+// LDS of a batched row block holding rows rows of nx nodes (pass A, or the
 // collision pass), and of a batched column block of col_elems nodes in
-// chunks of lc.
-size_t batch_row_lds(int rows_elems, bool collide);
-size_t batch_col_lds(int col_elems, int lc);
+// chunks of lc for strips of at most wmax columns.
+size_t batch_row_lds(int rows, int nx, bool collide);
+size_t batch_col_lds(int col_elems, int lc, int wmax);
 // Batched passes: rows use 256-thread workgroups (each mesh's rows_per_block
 // rows of nx <= 1024 nodes); the column pass uses col_elems / lc threads
 // (each mesh's cols_per_block = col_elems / ny columns), lc = 4 or 8.
 hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
                                  int nwork, int parity, size_t lds, hipStream_t s);
 hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
-                                int nwork, int col_elems, int lc, hipStream_t s);
+                                int nwork, int col_elems, int lc, int wmax, hipStream_t s);
 hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
                                      const WorkItem *work, int nwork, int parity, size_t lds,
                                      hipStream_t s);

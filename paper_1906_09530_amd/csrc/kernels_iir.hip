@@ -31,54 +31,103 @@ namespace {
 
 using namespace phys;
 
-// The thread's chunk within the block's lines.
+// Chunks carried on each side by the solve for chunk length lc: the weight
+// of the next chunk, |q|^(M lc), is below 2^-60 for both compact schemes
+// (alpha = 1/3 has the larger pole, |q| = 0.382, and sets M).
+constexpr int kCarry(int lc) { return lc == 4 ? 11 : (lc == 8 ? 6 : 3); }
+
+// The thread's chunk within the block's lines, and the LDS layout of a
+// block's line solves:
+//   values  n + 4 per line: the line with two ghost nodes at each end;
+//   cP, cB  nc + kCarry(LC) per line: one carry per chunk, with kCarry ghost
+//           chunks before the first (cP) or after the last (cB).
+// The ghosts hold the periodic images, or at walls the reflected values, so
+// the solve reads its neighbours without wrapping or testing indices.
+// Column layout (col): slot (index + offset) * nl + l; row layout: line l
+// contiguous.
 template <int LC>
 struct Chunk {
+    static constexpr int MC = kCarry(LC);
     int n;      // line length
     int nc;     // chunks per line (n / LC)
     int nl;     // lines held by the block (row or column count of the layout)
-    bool col;   // column layout: value slot j * nl + l, carry slot c * nl + l
+    bool col;
     bool mirror;
     int l, c;   // this thread's line and chunk
     bool ok;    // the line exists (ragged last block)
-    __device__ __forceinline__ int vslot(int j) const { return col ? j * nl + l : l * n + j; }
-    __device__ __forceinline__ int cslot(int ci) const { return col ? ci * nl + l : l * nc + ci; }
+    // value j in [-2, n + 2)
+    __device__ __forceinline__ int vslot(int j) const
+    {
+        return col ? (j + 2) * nl + l : l * (n + 4) + j + 2;
+    }
+    // cP of chunk ci in [-MC, nc), cB of chunk ci in [0, nc + MC)
+    __device__ __forceinline__ int pslot(int ci) const
+    {
+        return col ? (ci + MC) * nl + l : l * (nc + MC) + ci + MC;
+    }
+    __device__ __forceinline__ int bslot(int ci) const
+    {
+        return col ? ci * nl + l : l * (nc + MC) + ci;
+    }
 };
 
-// First derivative of u (parity par_u) along the thread's line; the whole
-// block calls it together.  vbuf: n*nl doubles of LDS; cP, cB: nc*nl each.
+// The block's LDS carved for the line solves (and the collision pass's edge
+// exchange: six planes of one slot per chunk, after the carries).
+struct LineLds {
+    double *vbuf, *cP, *cB, *edge;
+};
 template <int LC>
-__device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, int M, double qL,
-                                          const double (&u)[LC], double par_u, double *vbuf,
-                                          double *cP, double *cB, double (&d)[LC])
+__device__ __forceinline__ LineLds carve_lds(double *smem, const Chunk<LC> &m)
 {
-    const int j0 = m.c * LC, n = m.n;
+    LineLds L;
+    L.vbuf = smem;
+    L.cP = smem + (size_t)m.nl * (m.n + 4);
+    L.cB = L.cP + (size_t)m.nl * (m.nc + Chunk<LC>::MC);
+    L.edge = L.cB + (size_t)m.nl * (m.nc + Chunk<LC>::MC);
+    return L;
+}
+
+// First derivative of u (parity par_u) along the thread's line; the whole
+// block calls it together.
+template <int LC>
+__device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, double qL,
+                                          const double (&u)[LC], double par_u, const LineLds &L,
+                                          double (&d)[LC])
+{
+    constexpr int MC = Chunk<LC>::MC;
+    double *vbuf = L.vbuf, *cP = L.cP, *cB = L.cB;
+    const int j0 = m.c * LC, n = m.n, nc = m.nc;
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k) vbuf[m.vslot(j0 + k)] = u[k];
+        // ghost nodes: periodic images, or the even (par_u = 1) or odd
+        // (par_u = -1) reflection about the wall half a node past the end
+        if (m.c == 0) {
+            if (m.mirror) {
+                vbuf[m.vslot(-2)] = par_u * u[1];
+                vbuf[m.vslot(-1)] = par_u * u[0];
+            } else {
+                vbuf[m.vslot(n)] = u[0];
+                vbuf[m.vslot(n + 1)] = u[1];
+            }
+        }
+        if (m.c == nc - 1) {
+            if (m.mirror) {
+                vbuf[m.vslot(n)] = par_u * u[LC - 1];
+                vbuf[m.vslot(n + 1)] = par_u * u[LC - 2];
+            } else {
+                vbuf[m.vslot(-2)] = u[LC - 2];
+                vbuf[m.vslot(-1)] = u[LC - 1];
+            }
+        }
     }
     __syncthreads();
     const double q = p.iir_q;
     double r[LC], y[LC], z[LC];
-    double Pc = 0.0, Bc = 0.0;
     if (m.ok) {
-        double um2, um1, up0, up1;  // u at j0-2, j0-1, j0+LC, j0+LC+1
-        if (!m.mirror) {
-            int a = j0 - 2, b = j0 - 1, e = j0 + LC, f = j0 + LC + 1;
-            a = a < 0 ? a + n : a;
-            b = b < 0 ? b + n : b;
-            e = e >= n ? e - n : e;
-            f = f >= n ? f - n : f;
-            um2 = vbuf[m.vslot(a)];
-            um1 = vbuf[m.vslot(b)];
-            up0 = vbuf[m.vslot(e)];
-            up1 = vbuf[m.vslot(f)];
-        } else {
-            um2 = j0 >= 2 ? vbuf[m.vslot(j0 - 2)] : par_u * u[1];
-            um1 = j0 >= 1 ? vbuf[m.vslot(j0 - 1)] : par_u * u[0];
-            up0 = j0 + LC < n ? vbuf[m.vslot(j0 + LC)] : par_u * u[LC - 1];
-            up1 = j0 + LC + 1 < n ? vbuf[m.vslot(j0 + LC + 1)] : par_u * u[LC - 2];
-        }
+        // u at j0-2, j0-1, j0+LC, j0+LC+1
+        const double um2 = vbuf[m.vslot(j0 - 2)], um1 = vbuf[m.vslot(j0 - 1)];
+        const double up0 = vbuf[m.vslot(j0 + LC)], up1 = vbuf[m.vslot(j0 + LC + 1)];
         auto U = [&](int i) -> double {
             return i == -2 ? um2 : i == -1 ? um1 : i == LC ? up0 : i == LC + 1 ? up1 : u[i];
         };
@@ -91,30 +140,29 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
         z[LC - 1] = 0.0;
 #pragma unroll
         for (int k = LC - 2; k >= 0; --k) z[k] = q * (r[k + 1] + z[k + 1]);
-        Pc = y[LC - 1];
-        Bc = q * (r[0] + z[0]);
-        cP[m.cslot(m.c)] = Pc;
-        cB[m.cslot(m.c)] = Bc;
+        const double Pc = y[LC - 1];
+        const double Bc = q * (r[0] + z[0]);
+        cP[m.pslot(m.c)] = Pc;
+        cB[m.bslot(m.c)] = Bc;
+        // ghost chunks: periodic images, or at walls the carries of the
+        // reflected line (parity -par_u), which run the other way
+        if (m.mirror) {
+            const double par_r = -par_u;
+            if (m.c < MC) cP[m.pslot(-1 - m.c)] = par_r * p.iir_inv_q * Bc;
+            if (m.c >= nc - MC) cB[m.bslot(2 * nc - 1 - m.c)] = par_r * q * Pc;
+        } else {
+            if (m.c >= nc - MC) cP[m.pslot(m.c - nc)] = Pc;
+            if (m.c < MC) cB[m.bslot(m.c + nc)] = Bc;
+        }
     }
     __syncthreads();
     if (!m.ok) return;
-    const double par_r = -par_u;
-    const int nc = m.nc;
+    // the MC chunks on each side, nearest last (Horner in q^LC)
     double Yc = 0.0, Zc = 0.0;
-    for (int mm = M; mm >= 1; --mm) {
-        int a = m.c - mm, b = m.c + mm;
-        double pa, bb;
-        if (!m.mirror) {
-            a = a < 0 ? a + nc : a;
-            b = b >= nc ? b - nc : b;
-            pa = cP[m.cslot(a)];
-            bb = cB[m.cslot(b)];
-        } else {
-            pa = a >= 0 ? cP[m.cslot(a)] : par_r * p.iir_inv_q * cB[m.cslot(-1 - a)];
-            bb = b < nc ? cB[m.cslot(b)] : par_r * q * cP[m.cslot(2 * nc - 1 - b)];
-        }
-        Yc = Yc * qL + pa;
-        Zc = Zc * qL + bb;
+#pragma unroll
+    for (int mm = MC; mm >= 1; --mm) {
+        Yc = Yc * qL + cP[m.pslot(m.c - mm)];
+        Zc = Zc * qL + cB[m.bslot(m.c + mm)];
     }
 #pragma unroll
     for (int k = 0; k < LC; ++k)
@@ -172,7 +220,7 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     const size_t N = (size_t)nx * ny;
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
-    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + p.rows_per_block * m.nc;
+    const LineLds L = carve_lds(smem, m);
     const size_t base = (size_t)(y0 + m.l) * nx + m.c * LC;
     double rho[LC];
     if (m.ok) {
@@ -195,8 +243,8 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
         return;
     }
     double d1[LC], d2[LC];
-    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, d1);
-    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, d1, -1.0, vbuf, cP, cB, d2);
+    iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, d1);
+    iir_solve<LC>(p, m, p.iir_qL_row, d1, -1.0, L, d2);
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k) mx[k] -= p.kappa * d2[k];
@@ -242,7 +290,7 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
     m.c = threadIdx.x / W;
     m.l = threadIdx.x - m.c * W;
     m.ok = m.l < cols && m.c < m.nc;
-    double *vbuf = smem, *cP = smem + W * ny, *cB = cP + W * m.nc;
+    const LineLds L = carve_lds(smem, m);
     const size_t col = x0 + m.l;
     const int j0 = m.c * LC;
     double r[LC];
@@ -251,8 +299,8 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
         for (int k = 0; k < LC; ++k) r[k] = rho[(size_t)(j0 + k) * nx + col];
     }
     double dyr[LC], dyy[LC], mu[LC], dym[LC];
-    iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, r, 1.0, vbuf, cP, cB, dyr);
-    if (!p.kappa_zero) iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, dyr, -1.0, vbuf, cP, cB, dyy);
+    iir_solve<LC>(p, m, p.iir_qL_col, r, 1.0, L, dyr);
+    if (!p.kappa_zero) iir_solve<LC>(p, m, p.iir_qL_col, dyr, -1.0, L, dyy);
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k) {
@@ -263,7 +311,7 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
             mu_out[node] = v;
         }
     }
-    iir_solve<LC>(p, m, p.iir_m_col, p.iir_qL_col, mu, 1.0, vbuf, cP, cB, dym);
+    iir_solve<LC>(p, m, p.iir_qL_col, mu, 1.0, L, dym);
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k)
@@ -307,7 +355,7 @@ __device__ __forceinline__ void rows_collide_body(
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
     const int nlc = p.rows_per_block * m.nc;
-    double *vbuf = smem, *cP = smem + p.rows_per_block * nx, *cB = cP + nlc;
+    const LineLds L = carve_lds(smem, m);
     const int y = y0 + m.l, x0 = m.c * LC;
     const size_t base = (size_t)y * nx + x0;
     constexpr int NI = KEEP ? 9 : 1;
@@ -344,8 +392,8 @@ __device__ __forceinline__ void rows_collide_body(
         vload<LC>(mu + base, mv);
     }
     double dxr[LC], dxm[LC];
-    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, rho, 1.0, vbuf, cP, cB, dxr);
-    iir_solve<LC>(p, m, p.iir_m_row, p.iir_qL_row, mv, 1.0, vbuf, cP, cB, dxm);
+    iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, dxr);
+    iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
     double Fy[LC], Fx[LC];
     if (m.ok) {
         vload<LC>(fy + base, Fy);
@@ -369,7 +417,7 @@ __device__ __forceinline__ void rows_collide_body(
     // Edge exchange of the density groups: the value a chunk's first node
     // receives from the left neighbour (populations 1, 5, 8) and its last
     // node from the right neighbour (3, 6, 7), six slots per chunk.
-    double *edge = cB + nlc;
+    double *edge = L.edge;
     const int slot = m.l * m.nc + m.c;
     // the row's down-going groups bounce back at a bottom wall, the
     // up-going ones at a top wall
@@ -615,16 +663,23 @@ __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict
 
 }  // namespace
 
-// line values, the solve's two carry planes and (collision pass) six edge
-// planes, one slot per chunk each
-size_t batch_row_lds(int rows_elems, bool collide)
+// LDS of a block of nl lines of n nodes in chunks of lc: the values with
+// their ghosts, the two carry planes with theirs and (collision pass) the six
+// edge planes of one slot per chunk (the layout of Chunk and carve_lds).
+static size_t line_lds(int n, int nl, int lc, bool edges)
 {
-    return sizeof(double) * ((size_t)rows_elems + (collide ? 8 : 2) * (size_t)rows_elems / kRowLC);
+    const size_t nc = n / lc, L = nl;
+    return sizeof(double) * (L * (n + 4) + 2 * L * (nc + kCarry(lc)) + (edges ? 6 * L * nc : 0));
 }
 
-size_t batch_col_lds(int col_elems, int lc)
+size_t batch_row_lds(int rows, int nx, bool collide) { return line_lds(nx, rows, kRowLC, collide); }
+
+// every mesh's strip (w <= wmax columns of ny, w ny <= col_elems) fits
+size_t batch_col_lds(int col_elems, int lc, int wmax)
 {
-    return sizeof(double) * ((size_t)col_elems + 2 * (size_t)col_elems / lc);
+    const size_t W = wmax;
+    return sizeof(double) *
+           ((size_t)col_elems + 4 * W + 2 * ((size_t)col_elems / lc + W * kCarry(lc)));
 }
 
 hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
@@ -636,11 +691,11 @@ hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const
 }
 
 hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
-                                int nwork, int col_elems, int lc, hipStream_t s)
+                                int nwork, int col_elems, int lc, int wmax, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
     const int T = col_elems / lc;
-    const size_t lds = batch_col_lds(col_elems, lc);
+    const size_t lds = batch_col_lds(col_elems, lc, wmax);
     if (lc == 4 && T <= 256)
         hipLaunchKernelGGL((kb_cols_mu<4, 256>), dim3(nwork), dim3(T), lds, s, kps, sb, work);
     else if (lc == 4)
@@ -663,25 +718,26 @@ hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
 
 bool iir_rows_ok(const KParams &p)
 {
-    return p.nx >= kFastMinLine && p.nx % kRowLC == 0 &&
+    return p.nx >= kFastMinLine && p.nx % kRowLC == 0 && p.nx / kRowLC > kCarry(kRowLC) &&
+           p.iir_m_row <= kCarry(kRowLC) &&
            p.rows_per_block * (p.nx / kRowLC) <= kMaxBlockThreads;
 }
 
 bool iir_cols_ok(const KParams &p, int lc, int width)
 {
-    return p.ny >= kFastMinLine && p.ny % lc == 0 && width * (p.ny / lc) <= kMaxBlockThreads &&
+    return p.ny >= kFastMinLine && p.ny % lc == 0 && p.ny / lc > kCarry(lc) &&
+           p.iir_m_col <= kCarry(lc) && width * (p.ny / lc) <= kMaxBlockThreads &&
            width * p.ny <= kMaxBlockElems;
 }
 
 static size_t row_lds_iir(const KParams &p, bool collide)
 {
-    return batch_row_lds(p.rows_per_block * p.nx, collide);
+    return line_lds(p.nx, p.rows_per_block, kRowLC, collide);
 }
 
 static size_t col_lds_iir(const KParams &p)
 {
-    const size_t W = p.cols_per_block;
-    return sizeof(double) * (W * p.ny + 2 * W * (p.ny / p.col_lc));
+    return line_lds(p.ny, p.cols_per_block, p.col_lc, false);
 }
 
 static int row_threads_iir(const KParams &p) { return p.rows_per_block * (p.nx / kRowLC); }
