@@ -215,6 +215,63 @@ def copy_bandwidth(torch, nbytes, reps=20):
     return 2 * n * 8 / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
 
 
+SPLASH = dict(nx=4096, ny=2048, T_r=0.6, kappa=0.1, k=0.2, tau=0.6, mu_cap=6.0, radius=100.0,
+              width=5.0, film=40, drop_uy=-0.05, frame_ux=0.05, steps=10000)
+
+
+def splash_bench(torch, lbm, inputs):
+    """Drop falling on a liquid film between walls, 4096 x 2048 (CS), in the
+    rest frame and in a frame moving at +0.05 with the walls sliding along:
+    MLUPS of each (autotuned, chunks of 1000 steps with the moments read after
+    each), mass at start and end, and the Galilean check (the moving-frame
+    density shifted back by frame_ux x steps nodes against the rest frame)."""
+    import numpy as np
+    c = SPLASH
+    nx, ny = c["nx"], c["ny"]
+    res, runs = {}, []
+    for frame in (0.0, c["frame_ux"]):
+        p = lbm.params(lbm.EOS_CS, c["T_r"], nx, ny, kappa=c["kappa"], tau=c["tau"], k=c["k"],
+                       mu_cap=c["mu_cap"], bc_y=1, wall_ux=frame)
+        g, l = lbm.maxwell(p)
+        rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, c["radius"], c["width"], film=c["film"],
+                                       drop_uy=c["drop_uy"], frame_ux=frame)
+        d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+        s = lbm.Solver(p, *d)
+        s.autotune(5)
+        mass0 = float(rho0.sum())
+        done, t_step = 0, 0.0
+        finite = True
+        while done < c["steps"]:
+            n = min(1000, c["steps"] - done)
+            t0 = time.perf_counter()
+            s.step(n)
+            s.synchronize()
+            t_step += time.perf_counter() - t0
+            done += n
+            r = s.moments()[0]
+            finite = bool(np.isfinite(r).all())
+            print("splash frame %.2f: %d steps, finite %s" % (frame, done, finite),
+                  file=sys.stderr, flush=True)
+            if not finite:
+                break
+        s.close()
+        res[frame] = r
+        runs.append({"frame_ux": frame, "steps": done, "finite": finite, "mass_start": mass0,
+                     "mass_end": float(r.sum()), "seconds": round(t_step, 3),
+                     "MLUPS": round(nx * ny * done / t_step / 1e6, 1)})
+    out = dict(c, workload="drop splashing on a film between walls, CS", runs=runs)
+    if all(r["finite"] for r in runs):
+        shift = int(round(c["frame_ux"] * c["steps"]))
+        moved = np.roll(res[c["frame_ux"]], -shift, axis=1)
+        half = 0.5 * (g + l)
+        out["galilean"] = {
+            "shift_nodes": shift,
+            "max_abs_drho": float(np.abs(moved - res[0.0]).max()),
+            "nodes_across_mid_density_contour": int(((res[0.0] > half) != (moved > half)).sum()),
+            "nodes": nx * ny}
+    return out
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -260,6 +317,9 @@ def main():
     ap.add_argument("--sweep", choices=["small", "full", "none"], default="small",
                     help="batched sweep vs one run per member (time to converge): 16 members "
                          "up to 256^2 (small), 64 members up to 512^2 (full, minutes), or none")
+    ap.add_argument("--splash", choices=["full", "none"], default="none",
+                    help="also run the 4096 x 2048 splash between walls in two frames "
+                         "(10,000 steps each, about 20 s)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, to calibrate FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -342,6 +402,7 @@ def main():
     traffic = measured_traffic(PASS_NAMES[dom])
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
     warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)
+    splash = None if args.splash == "none" else splash_bench(torch, lbm, inputs)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     out = {
         "metric": METRIC,
@@ -389,6 +450,7 @@ def main():
                   "rho_g_maxwell": rho_g, "rho_l_maxwell": rho_l},
         "sweep": sweep,
         "warm_start": warm,
+        "splash": splash,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
