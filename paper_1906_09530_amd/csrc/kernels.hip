@@ -4,14 +4,18 @@
 // A step is three passes over the mesh:
 //   A (rows)    rho = sum_i f_i (Eq. 3); d/dx rho and d2/dx2 rho by the
 //               compact scheme (Eqs. 37-39, second derivative by applying it
-//               twice, Sec. 4.3).  Writes rho and d2/dx2 rho.
-//   B (columns) d/dy rho, d2/dy2 rho, the mesh chemical potential
-//               mu = k^2 psi'(rho) - kappa lap(rho) (Eq. 33) with psi'
-//               bounded by the upper limit of Sec. 5.6, d/dy mu and
-//               F_y = -rho d/dy mu + c_s^2 d/dy rho (Eq. 12).  Writes mu, F_y.
+//               twice, Sec. 4.3); the row part of the mesh chemical potential
+//               (Eq. 33), k^2 psi'(rho) - kappa d2rho/dx2, with psi' bounded
+//               by the upper limit of Sec. 5.6.  Writes rho and the row part.
+//               (The fast kernels of kernels_iir.hip take rho from the three
+//               density groups the previous collision wrote.)
+//   B (columns) d/dy rho, d2/dy2 rho, mu = row part - kappa d2rho/dy2,
+//               d/dy mu and F_y = -rho d/dy mu + c_s^2 d/dy rho (Eq. 12).
+//               Writes mu, F_y.
 //   C (rows)    d/dx rho, d/dx mu, F_x; BGK collision with the
 //               exact-difference force term (Eqs. 1, 2, 5) and push-streaming
-//               into the other distribution buffer.
+//               into the other distribution buffer (and, fast kernels, its
+//               density groups).
 //
 // Line solves.  Eq. 37 on a periodic line is the circulant system
 //   d_i + al (d_{i-1} + d_{i+1}) = r_i.

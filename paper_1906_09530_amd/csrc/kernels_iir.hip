@@ -17,11 +17,13 @@
 // and then adds the contributions of the M chunks before and after it,
 //     y_k += q^(k+1) sum_{m=1..M} q^((m-1)LC) P_{c-m},
 //     z_k += q^(LC-1-k) sum_{m=1..M} q^((m-1)LC) B_{c+m},
-// with M the smallest count for which |q|^(M LC) < 2^-60.  Two barriers per
-// solve.  Between walls the column is the even extension of length 2 ny:
-// a chunk beyond a wall is the mirror image of a physical chunk, whose P and B
-// swap roles (P of the image of chunk i is par B_i / q, B of the image is
-// par q P_i, par being the parity of the right-hand side).
+// with M = kCarry(LC) chunks, enough that |q|^(M LC) < 2^-60 for either
+// scheme.  Two barriers per solve.  Between walls the column is the even
+// extension of length 2 ny: a chunk beyond a wall is the mirror image of a
+// physical chunk, whose P and B swap roles (P of the image of chunk i is
+// par B_i / q, B of the image is par q P_i, par being the parity of the
+// right-hand side).  Ghost slots in LDS hold these images (and the periodic
+// ones), so the solve reads neighbours without tests (see Chunk).
 #include "kernels.hpp"
 #include "physics.hpp"
 
