@@ -165,16 +165,30 @@ lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int 
 /* Autotuner: time the column pass of the current state for each strip width
  * (columns per workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS
  * holds and, for the factorised solve, each chunk length (column nodes per
- * thread) in {4, 8, 16}; then time the collision pass holding the nine
- * populations in registers or reading them twice.  `repeats` launches each
+ * thread) in {4, 8, 16}; then time the collision pass variants of
+ * lbm_set_collision_variant that the mesh allows.  `repeats` launches each
  * (HIP events); keep the fastest of each for the context.  The state f is
  * not changed.  widths[], chunks[] and ms[] (room for 17 entries each, may be
  * NULL) receive the candidates and their average time in milliseconds --
  * column candidates as (width, chunk; chunk 0 = general reduction kernel),
- * collision candidates as (0, 1 = registers / 0 = read twice) -- and *count
- * (may be NULL) their number.  Synchronises. */
+ * collision candidates as (0, variant) -- and *count (may be NULL) their
+ * number.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, double *ms,
                         int *count);
+
+/* Collision pass variant (pass C of Eqs. 1, 2, 5, 12), for meshes whose rows
+ * take the factorised-inverse kernels; the autotuner picks among them.
+ *   0  one kernel over whole rows, reading the populations twice;
+ *   1  one kernel over whole rows holding the populations in registers
+ *      (rows of at most 1024 nodes; the default there);
+ *   2  split for long rows (at least 2048 nodes, a multiple of 1024): F_x
+ *      over whole rows from the density and mu planes, then the collision
+ *      over 1024-node row segments holding the populations in registers.
+ *      F_x then takes rho from pass A (the sum of the density groups)
+ *      instead of the collision's own sum of f, so results differ from
+ *      variants 0 and 1 in the last bits.
+ * LBM_E_INVALID if the variant is not available for this mesh. */
+lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
 
 /* Set the column-pass shape directly (width in columns per workgroup, chunk
  * in column nodes per thread of the factorised solve, 0 for the general

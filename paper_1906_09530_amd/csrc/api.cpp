@@ -235,7 +235,8 @@ lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
         double *fn = c->f[1 - c->cur];
         HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, c->stream));
         HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
-        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->stream));
+        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->rho,
+                                      c->obs, c->stream));
         c->cur = 1 - c->cur;
         c->steps += 1;
     }
@@ -258,6 +259,29 @@ lbm_status copy_out(lbm_ctx *c, double *dst, const double *src, size_t n, int on
                              on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                              c->stream));
     return LBM_OK;
+}
+
+// Collision pass variant (fast rows only): 0 one pass reading f twice,
+// 1 one pass holding f in registers (rows of up to 1024 nodes), 2 split into
+// F_x over whole rows and the collision over row segments holding f in
+// registers (rows of at least 2048 nodes in whole 1024-node segments).
+bool collision_variant(KParams *kp, int variant)
+{
+    const bool rows256 = kp->rows_per_block * (kp->nx / kIirRowChunk) <= 256;
+    switch (variant) {
+    case 0: kp->row_keep = 0; kp->row_split = 0; return true;
+    case 1:
+        if (!kp->use_iir_rows || !rows256) return false;
+        kp->row_keep = 1;
+        kp->row_split = 0;
+        return true;
+    case 2:
+        if (!iir_split_ok(*kp)) return false;
+        kp->row_keep = 1;
+        kp->row_split = 1;
+        return true;
+    default: return false;
+    }
 }
 
 lbm_status enter(lbm_ctx *c)
@@ -549,7 +573,9 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
         for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
             if (q == 0) err = launch_rows_rho(c->kp, fc, gc, c->rho, c->mux, c->stream);
             if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
-            if (q == 2) err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->stream);
+            if (q == 2)
+                err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs,
+                                          c->stream);
         }
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -609,21 +635,22 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         }
     }
     if (err == hipSuccess) set_col_shape(&c->kp, best_w, best_c);
-    // collision pass: populations held in registers or read twice.  It reads
-    // the current f, mu and F_y and writes only the spare buffers, so the
-    // state is untouched; mu and F_y are refreshed first with the chosen shape.
+    // collision pass: populations held in registers or read twice, in one
+    // pass or split for long rows.  It reads the current f, rho, mu and F_y
+    // and writes only the spare buffers (and the scratch plane), so the state
+    // is untouched; mu and F_y are refreshed first with the chosen shape.
     if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
     double best_row = INFINITY;
-    int best_keep = c->kp.row_keep;
-    for (int keep = 0; keep < 2 && err == hipSuccess; ++keep) {
+    int best_variant = c->kp.row_split ? 2 : c->kp.row_keep;
+    for (int variant = 0; variant < 3 && err == hipSuccess; ++variant) {
         KParams kp = c->kp;
-        kp.row_keep = keep;
+        if (!collision_variant(&kp, variant)) continue;
         const double *fc = c->f[c->cur];
         double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
-        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->stream);
+        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
         for (int r = 0; r < repeats && err == hipSuccess; ++r)
-            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->stream);
+            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float t = 0.f;
@@ -631,20 +658,31 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         if (err != hipSuccess) break;
         const double avg = t / repeats;
         if (widths) widths[n] = 0;
-        if (chunks) chunks[n] = keep;
+        if (chunks) chunks[n] = variant;
         if (ms) ms[n] = avg;
         ++n;
         if (avg < best_row) {
             best_row = avg;
-            best_keep = keep;
+            best_variant = variant;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess)
         return fail(c, LBM_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(err));
-    c->kp.row_keep = best_keep;
+    (void)collision_variant(&c->kp, best_variant);
     if (count) *count = n;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_collision_variant(lbm_ctx *c, int variant)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    KParams kp = c->kp;
+    if (!collision_variant(&kp, variant))
+        return fail(c, LBM_E_INVALID, "collision variant not available for this mesh");
+    c->kp = kp;
     return LBM_OK;
 }
 

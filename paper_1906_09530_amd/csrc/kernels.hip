@@ -444,6 +444,8 @@ void set_row_shape(KParams *p)
     p->rows_per_block = R;
     p->row_threads = round_threads(R * p->nx);
     p->use_iir_rows = iir_rows_ok(*p);
+    p->seg_len = kSegLen;
+    p->row_split = 0;
 }
 
 void set_col_shape(KParams *p, int width, int chunk)
@@ -500,8 +502,11 @@ hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux
 }
 
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *fout, double *gout, hipStream_t s)
+                               const double *fy, double *fout, double *gout, const double *rho,
+                               double *fx, hipStream_t s)
 {
+    if (p.use_iir_rows && p.row_split)
+        return launch_collide_split_iir(p, f, rho, mu, fy, fx, fout, gout, s);
     if (p.use_iir_rows)
         return launch_rows_collide_iir(p, f, mu, fy, fout, gout, nullptr, nullptr, nullptr,
                                        nullptr, false, s);

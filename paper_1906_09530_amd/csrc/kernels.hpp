@@ -30,13 +30,16 @@ struct KParams {
     // pole q, 1/q, K = 1/(1 + 2 al q), powers q^0..q^16, and per pass the
     // chunk length, its power q^LC and the number of carried chunks M
     int use_iir_rows, use_iir_cols, col_lc;
-    int row_keep;  // collision pass holds f in registers (tuned)
+    int row_keep;   // collision pass holds f in registers (tuned)
+    int row_split;  // collision pass split for long rows (tuned; see below)
+    int seg_len;    // row segment of the split collision pass
     int iir_m_row, iir_m_col;
     double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
     double iir_qp[17];
 };
 
 constexpr int kIirRowChunk = 4;
+constexpr int kSegLen = 1024;  // nodes per segment of the split collision pass
 
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
@@ -56,9 +59,12 @@ hipError_t launch_rows_rho(const KParams &p, const double *f, const double *g, d
 hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux, double *mu,
                           double *fy, hipStream_t s);
 // Pass C over rows: d/dx rho, d/dx mu, F_x, collision and streaming f -> fout,
-// and (fast kernels) the density groups gout of fout.
+// and (fast kernels) the density groups gout of fout.  rho: pass A's density
+// plane and fx: N doubles of scratch, both used by the split variant
+// (row_split) only.
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *fout, double *gout, hipStream_t s);
+                               const double *fy, double *fout, double *gout, const double *rho,
+                               double *fx, hipStream_t s);
 // Pass C in observation mode: rho, v = u + F/(2 rho), F_x (any output may be null).
 hipError_t launch_rows_observe(const KParams &p, const double *f, const double *mu,
                                const double *fy, double *rho, double *vx, double *vy,
@@ -122,5 +128,12 @@ hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const doub
                                    const double *fy, double *fout, double *gout, double *o_rho,
                                    double *o_vx, double *o_vy, double *o_fx, bool observe,
                                    hipStream_t s);
+// Split collision pass for rows of at least 2 kSegLen nodes in whole
+// segments: F_x over whole rows into fx (N doubles of scratch, from the rho
+// and mu planes), then the collision over row segments into (fout, gout).
+bool iir_split_ok(const KParams &p);
+hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
+                                    const double *mu, const double *fy, double *fx,
+                                    double *fout, double *gout, hipStream_t s);
 
 }  // namespace cplbm

@@ -208,6 +208,22 @@ __device__ __forceinline__ Chunk<LC> row_chunk(const KParams &p, int rows)
 
 constexpr int kRowLC = 4;
 
+// Segment chunk of this thread: one segment of seg_len nodes of one row.
+template <int LC>
+__device__ __forceinline__ Chunk<LC> seg_chunk(const KParams &p)
+{
+    Chunk<LC> m;
+    m.n = p.seg_len;
+    m.nc = p.seg_len / LC;
+    m.nl = 1;
+    m.col = false;
+    m.mirror = false;
+    m.l = 0;
+    m.c = threadIdx.x;
+    m.ok = m.c < m.nc;
+    return m;
+}
+
 // Pass A on rows [y0, y0 + rows_per_block) of one mesh: rho, and the row part
 // of the chemical potential of Eq. 33, k^2 psi'(rho) - kappa d2rho/dx2.
 // rho comes from the state's three density groups g (written by the previous
@@ -343,22 +359,28 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
 // reads 3 planes instead of 9.  Each group is summed in this order whatever
 // the source of its members (shifted along the row, or bounced back at a
 // wall), so the groups are a function of fout alone.
-template <bool OBSERVE, bool KEEP>
+//
+// SEG: the split variant for long rows.  The block holds one segment
+// [xs, xs + seg_len) of row y0 and takes F_x from fx_in (written by the
+// derivative pass k_rows_fx_iir), so it has no line solve; the density groups
+// of the segment's first and last node, which receive populations from the
+// neighbouring segments, are left to k_group_seams.
+template <bool OBSERVE, bool KEEP, bool SEG = false>
 __device__ __forceinline__ void rows_collide_body(
     const KParams &p, int y0, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
     double *__restrict__ o_rho, double *__restrict__ o_vx, double *__restrict__ o_vy,
-    double *__restrict__ o_fx)
+    double *__restrict__ o_fx, int xs = 0, const double *__restrict__ fx_in = nullptr)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
-    const int rows = min(p.rows_per_block, ny - y0);
-    const Chunk<LC> m = row_chunk<LC>(p, rows);
-    const int nlc = p.rows_per_block * m.nc;
+    const int rows = SEG ? 1 : min(p.rows_per_block, ny - y0);
+    const Chunk<LC> m = SEG ? seg_chunk<LC>(p) : row_chunk<LC>(p, rows);
+    const int nlc = SEG ? m.nc : p.rows_per_block * m.nc;
     const LineLds L = carve_lds(smem, m);
-    const int y = y0 + m.l, x0 = m.c * LC;
+    const int y = y0 + m.l, x0 = xs + m.c * LC;
     const size_t base = (size_t)y * nx + x0;
     constexpr int NI = KEEP ? 9 : 1;
     double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
@@ -391,16 +413,23 @@ __device__ __forceinline__ void rows_collide_body(
                 }
             }
         }
-        vload<LC>(mu + base, mv);
+        if (!SEG) vload<LC>(mu + base, mv);
     }
-    double dxr[LC], dxm[LC];
-    iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, dxr);
-    iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
     double Fy[LC], Fx[LC];
-    if (m.ok) {
-        vload<LC>(fy + base, Fy);
+    if (SEG) {
+        if (m.ok) {
+            vload<LC>(fy + base, Fy);
+            vload<LC>(fx_in + base, Fx);
+        }
+    } else {
+        double dxr[LC], dxm[LC];
+        iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, dxr);
+        iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
+        if (m.ok) {
+            vload<LC>(fy + base, Fy);
 #pragma unroll
-        for (int k = 0; k < LC; ++k) Fx[k] = -rho[k] * dxm[k] + CS2 * dxr[k];
+            for (int k = 0; k < LC; ++k) Fx[k] = -rho[k] * dxm[k] + CS2 * dxr[k];
+        }
     }
     if (OBSERVE) {
         if (!m.ok) return;
@@ -608,9 +637,19 @@ __device__ __forceinline__ void rows_collide_body(
     }
     // g0 of this row; g1 of the row above (of this row at a top wall, as
     // g2); g2 of the row below (of this row at a bottom wall, as g1)
-    vstore<LC>(gout + base, gm);
     const size_t up = refl_u ? 2 * N + base : N + (size_t)(y + 1 < ny ? y + 1 : 0) * nx + x0;
     const size_t dn = refl_d ? N + base : 2 * N + (size_t)(y > 0 ? y - 1 : ny - 1) * nx + x0;
+    if (SEG && (m.c == 0 || m.c == m.nc - 1)) {
+        // a segment's end node: its groups come from k_group_seams
+        const int k0 = m.c == 0 ? 1 : 0, k1 = m.c == m.nc - 1 ? LC - 1 : LC;
+        for (int k = k0; k < k1; ++k) {
+            gout[base + k] = gm[k];
+            gout[up + k] = gu[k];
+            gout[dn + k] = gd[k];
+        }
+        return;
+    }
+    vstore<LC>(gout + base, gm);
     vstore<LC>(gout + up, gu);
     vstore<LC>(gout + dn, gd);
 }
@@ -624,6 +663,79 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
 {
     rows_collide_body<OBSERVE, KEEP>(p, blockIdx.x * p.rows_per_block, f, mu, fy, fout, gout,
                                      o_rho, o_vx, o_vy, o_fx);
+}
+
+// ---- split collision pass for long rows -------------------------------
+// Rows longer than one 256-thread workgroup holds with the populations in
+// registers run pass C as two kernels: the row derivatives and F_x over whole
+// rows (k_rows_fx_iir), then the collision without a line solve over
+// 1024-node row segments in 256-thread workgroups that hold f in registers
+// (k_collide_seg_iir); k_group_seams then forms the density groups of the
+// segments' end nodes from the finished f.
+
+// F_x = -rho d/dx mu + c_s^2 d/dx rho (Eq. 12) from the rho and mu planes.
+__device__ __forceinline__ void rows_fx_body(const KParams &p, int y0,
+                                             const double *__restrict__ rho,
+                                             const double *__restrict__ mu,
+                                             double *__restrict__ fx_out)
+{
+    constexpr int LC = kRowLC;
+    extern __shared__ double smem[];
+    const int rows = min(p.rows_per_block, p.ny - y0);
+    const Chunk<LC> m = row_chunk<LC>(p, rows);
+    const LineLds L = carve_lds(smem, m);
+    const size_t base = (size_t)(y0 + m.l) * p.nx + m.c * LC;
+    double r[LC], mv[LC];
+    if (m.ok) {
+        vload<LC>(rho + base, r);
+        vload<LC>(mu + base, mv);
+    }
+    double dxr[LC], dxm[LC];
+    iir_solve<LC>(p, m, p.iir_qL_row, r, 1.0, L, dxr);
+    iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
+    if (m.ok) {
+        double Fx[LC];
+#pragma unroll
+        for (int k = 0; k < LC; ++k) Fx[k] = -r[k] * dxm[k] + CS2 * dxr[k];
+        vstore<LC>(fx_out + base, Fx);
+    }
+}
+
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_rows_fx_iir(KParams p, const double *__restrict__ rho,
+                                                      const double *__restrict__ mu,
+                                                      double *__restrict__ fx_out)
+{
+    rows_fx_body(p, blockIdx.x * p.rows_per_block, rho, mu, fx_out);
+}
+
+template <bool KEEP>
+__global__ __launch_bounds__(256) void k_collide_seg_iir(
+    KParams p, const double *__restrict__ f, const double *__restrict__ fy,
+    const double *__restrict__ fx, double *__restrict__ fout, double *__restrict__ gout)
+{
+    const int nseg = p.nx / p.seg_len;
+    const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
+    rows_collide_body<false, KEEP, true>(p, y, f, nullptr, fy, fout, gout, nullptr, nullptr,
+                                         nullptr, nullptr, sg * p.seg_len, fx);
+}
+
+// Density groups (as k_density_groups) at the first and last node of every
+// segment of every row.
+__global__ void k_group_seams(KParams p, const double *__restrict__ f, double *__restrict__ g)
+{
+    const int nseg = p.nx / p.seg_len;
+    const size_t N = (size_t)p.nx * p.ny, total = (size_t)p.ny * nseg * 2;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t y = i / (2 * nseg);
+        const int j = (int)(i - y * 2 * nseg);
+        const int x = (j >> 1) * p.seg_len + ((j & 1) ? p.seg_len - 1 : 0);
+        const size_t n = y * p.nx + x;
+        g[n] = (f[n] + f[N + n]) + f[3 * N + n];
+        g[N + n] = (f[2 * N + n] + f[5 * N + n]) + f[6 * N + n];
+        g[2 * N + n] = (f[4 * N + n] + f[7 * N + n]) + f[8 * N + n];
+    }
 }
 
 // ---- batched passes: one launch covers the blocks of every active mesh ----
@@ -774,6 +886,37 @@ hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double 
     default: CPLBM_IIR_THREADS(T, (k_cols_mu_iir<16, 256>), (k_cols_mu_iir<16, 1024>), ARGS); break;
     }
 #undef ARGS
+    return hipGetLastError();
+}
+
+bool iir_split_ok(const KParams &p)
+{
+    return p.use_iir_rows && p.nx >= 2 * kSegLen && p.nx % kSegLen == 0;
+}
+
+hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
+                                    const double *mu, const double *fy, double *fx,
+                                    double *fout, double *gout, hipStream_t s)
+{
+    if (!iir_split_ok(p) || p.seg_len != kSegLen) return hipErrorInvalidValue;
+    const int T = row_threads_iir(p);
+#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, rho, mu, fx
+    CPLBM_IIR_THREADS(T, k_rows_fx_iir<256>, k_rows_fx_iir<1024>, ARGS);
+#undef ARGS
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int blocks = p.ny * (p.nx / kSegLen);
+    const size_t lds = line_lds(kSegLen, 1, kRowLC, true);
+    if (p.row_keep)
+        hipLaunchKernelGGL(k_collide_seg_iir<true>, dim3(blocks), dim3(kSegLen / kRowLC), lds, s,
+                           p, f, fy, fx, fout, gout);
+    else
+        hipLaunchKernelGGL(k_collide_seg_iir<false>, dim3(blocks), dim3(kSegLen / kRowLC), lds, s,
+                           p, f, fy, fx, fout, gout);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t seams = (size_t)p.ny * (p.nx / kSegLen) * 2;
+    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
+                       (const double *)fout, gout);
     return hipGetLastError();
 }
 

@@ -80,6 +80,7 @@ def load():
         "lbm_autotune": (i32, [P, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), pd,
                             C.POINTER(C.c_int)]),
         "lbm_set_column_shape": (i32, [P, i32, i32]),
+        "lbm_set_collision_variant": (i32, [P, i32]),
         "lbm_steps_taken": (i64, [P]),
         "lbm_synchronize": (i32, [P]),
         "lbm_destroy": (None, [P]),
@@ -243,6 +244,11 @@ class Solver:
         n = C.c_int()
         _check(load().lbm_autotune(self.ctx, int(repeats), w, ch, ms, C.byref(n)), self.ctx)
         return {(w[i], ch[i]): ms[i] for i in range(n.value)}
+
+    def set_collision_variant(self, variant):
+        """0: one pass reading f twice; 1: one pass, f in registers; 2: split
+        for rows of >= 2048 nodes (derivative pass + segmented collision)."""
+        _check(load().lbm_set_collision_variant(self.ctx, int(variant)), self.ctx)
 
     def set_column_shape(self, width, chunk):
         _check(load().lbm_set_column_shape(self.ctx, int(width), int(chunk)), self.ctx)

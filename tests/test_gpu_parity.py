@@ -405,3 +405,40 @@ def test_other_equations_of_state(eos):
     g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 20.0, 6.0, seed=3, noise=1e-6)
     _run_case("eos%d" % eos, p, op, rho0, ux0, uy0, [100, 300])
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(2048, 48, 0), (3072, 40, 1)])
+def test_split_collision_for_long_rows(nx, ny, walls):
+    """The split collision variant (F_x over whole rows, then the collision
+    over 1024-node row segments, then the density groups of the segments'
+    end nodes): parity with the oracle after 100 and 200 steps; a run resumed
+    from its own state ends bitwise where the uninterrupted one does (the
+    groups formed at the seams equal those of f); and the whole-row variant
+    agrees to round-off."""
+    p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                         bc_y=walls)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, ny / 4.0, 3.0, seed=23, noise=1e-4,
+                                    center=(1023.5, ny / 2.0))
+    ref = _oracle_after(op, rho0, ux0, uy0, [100, 200])
+    a = lbm.Solver(p, rho0, ux0, uy0)
+    a.set_collision_variant(2)
+    a.step(100)
+    mid = a.get_state()
+    er, ev = _errors(a.moments(), ref[100])
+    a.step(100)
+    er2, ev2 = _errors(a.moments(), ref[200])
+    print("\nsplit %dx%d walls=%d: rho %.2e %.2e, v %.2e %.2e" % (nx, ny, walls, er, er2, ev, ev2))
+    assert max(er, er2, ev, ev2) <= TOL
+    b = lbm.Solver(p, rho0, ux0, uy0)
+    b.set_collision_variant(2)
+    b.set_state(mid)
+    b.step(100)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    c = lbm.Solver(p, rho0, ux0, uy0)
+    c.set_collision_variant(0)
+    c.step(200)
+    erc, evc = _errors(c.moments(), a.moments())
+    assert erc <= 1e-12 and evc <= 1e-10
+    with pytest.raises(lbm.LBMError):
+        lbm.Solver(p, rho0, ux0, uy0).set_collision_variant(1)   # rows need 1024 threads
