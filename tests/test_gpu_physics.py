@@ -7,13 +7,16 @@ bounds follow what the BGK scheme with the exact-difference force reaches at
 these settings (measured; the deviations are properties of the scheme, shared
 by the oracle):
 
-* flat slab, CS, T/Tc = 0.85, k = 0.2, 8-node interface: liquid within 1e-4 of
-  Maxwell, gas within 1e-3 (measured 4e-6 and 1.1e-4);
-* drops, same settings, R = 32 ... 96 (radius at least four interface
-  widths): the pressure jump k^2 [p0(rho_in) - p0(rho_out)] times the
-  equimolar radius is the same for every drop to 3 % (Laplace's law, measured
-  1.2 %); the surface tension it implies exceeds the continuum
-  sigma = k sqrt(kappa) sigma_1 by 1.77x.  The flat interface shows why: the
+* flat slabs, CS, T/Tc = 0.5 ... 0.85, k = 0.2 ... 0.4, interfaces of 5 and 8
+  nodes: liquid within 2e-5 of Maxwell everywhere (measured <= 8.3e-6), gas
+  within 1e-3 at T/Tc = 0.85 (measured 1.1e-4) and above Maxwell by an amount
+  that grows as T falls (3.7e-2 at 0.5);
+* drops, T/Tc = 0.85 and 0.75, k = 0.2, 8-node interface, R = 32 ... 96
+  (radius at least four interface widths): the pressure jump
+  k^2 [p0(rho_in) - p0(rho_out)] times the equimolar radius is the same for
+  every drop to 3 % (Laplace's law, measured 1.2 %); the surface tension it
+  implies exceeds the continuum sigma = k sqrt(kappa) sigma_1 by 1.77x
+  (0.85) and 1.50x (0.75).  The flat interface shows why: the
   forced lattice carries a bare velocity u = -F/(2 rho) inside the interface,
   whose momentum flux F F/(4 rho) adds normal stress; summed over the
   interface it is of the size of the excess (it predicts 2.2x).
@@ -30,9 +33,9 @@ pytestmark = pytest.mark.gpu
 T_R, K, W = 0.85, 0.2, 8.0
 
 
-def _settings():
+def _settings(T_r=T_R):
     e = A.EOS(A.EOS_CS)
-    it = e.interface(T_R)
+    it = e.interface(T_r)
     w1 = float(mp.re(it["width1"]))
     kappa = (W * K / w1) ** 2
     return e, it, kappa
@@ -46,36 +49,63 @@ def _converge(b, n, max_chunks=20):
     assert all(s == lbm.LBM_OK for s in sts), sts
 
 
-def test_flat_slab_meets_the_maxwell_densities():
-    _, _, kappa = _settings()
-    g, l = A.coexistence(A.EOS_CS, T_R)
+# (T/Tc, k, interface width W) of the flat-slab table; k = 0.3 with W = 8 and
+# k = 0.4 with W >= 5 diverge at T/Tc <= 0.6 (stability of the explicit scheme)
+SLABS = [(0.50, 0.2, 5.0), (0.50, 0.2, 8.0), (0.60, 0.2, 8.0), (0.70, 0.2, 8.0),
+         (0.70, 0.3, 8.0), (0.85, 0.2, 8.0), (0.85, 0.4, 8.0)]
+
+
+def test_flat_slabs_against_the_maxwell_densities():
+    """Flat slabs, 64 x 384 (liquid in the middle half), CS, tau = 1,
+    kappa = (W k / w1)^2, run as one batch to convergence.  Liquid within
+    2e-5 of Maxwell everywhere (measured <= 8.3e-6); the gas within 1e-3 at
+    T/Tc = 0.85 (measured 1.1e-4, 1.4e-4) and above Maxwell by an amount that
+    grows as T falls (3.7e-2 at 0.5) -- the excess normal stress of the
+    forced lattice, see the module docstring; every slab stays flat."""
+    e = A.EOS(A.EOS_CS)
     nx, ny = 64, 384
-    p = lbm.params(lbm.EOS_CS, T_R, nx, ny, kappa=kappa, tau=1.0, k=K)
-    b = lbm.Batch([p], [inputs.slab(nx, ny, g, l, W)[0]])
-    _converge(b, 1)
-    r = b.moments(0)[0]
-    rl, rg = r[ny // 2, 0], r[0, 0]
-    print("\nslab T/Tc %.2f: rho_l %+.2e, rho_g %+.2e relative to Maxwell" % (
-        T_R, rl / l - 1, rg / g - 1), flush=True)
-    assert abs(rl / l - 1) <= 1e-4
-    assert abs(rg / g - 1) <= 1e-3
-    assert (r == r[:, :1]).all()  # stays flat
+    ps, r0, ml = [], [], []
+    for T_r, k, W in SLABS:
+        w1 = float(mp.re(e.interface(T_r)["width1"]))
+        g, l = A.coexistence(A.EOS_CS, T_r)
+        ps.append(lbm.params(lbm.EOS_CS, T_r, nx, ny, kappa=(W * k / w1) ** 2, tau=1.0, k=k))
+        r0.append(inputs.slab(nx, ny, g, l, W)[0])
+        ml.append((g, l))
+    b = lbm.Batch(ps, r0)
+    _converge(b, len(ps))
+    dev = {}
+    print("\n T/Tc    k    W   kappa   rho_l-Maxwell  rho_g-Maxwell")
+    for i, (T_r, k, W) in enumerate(SLABS):
+        r = b.moments(i)[0]
+        g, l = ml[i]
+        dl, dg = r[ny // 2, 0] / l - 1, r[0, 0] / g - 1
+        dev[(T_r, k, W)] = (dl, dg)
+        print(" %.2f  %.1f  %.0f  %.4f   %+.2e      %+.2e" % (T_r, k, W, ps[i].kappa, dl, dg),
+              flush=True)
+        assert (r == r[:, :1]).all()      # stays flat
+        assert abs(dl) <= 2e-5
+        assert 0.0 < dg <= 0.1
+    assert dev[(0.85, 0.2, 8.0)][1] <= 1e-3 and dev[(0.85, 0.4, 8.0)][1] <= 1e-3
+    gas = [dev[(T, 0.2, 8.0)][1] for T in (0.5, 0.6, 0.7, 0.85)]
+    assert all(a > b for a, b in zip(gas, gas[1:]))
 
 
-def test_drops_follow_laplaces_law():
-    e, it, kappa = _settings()
+@pytest.mark.parametrize("T_r", [0.85, 0.75])
+def test_drops_follow_laplaces_law(T_r):
+    e, it, kappa = _settings(T_r)
     T, al = it["T"], it["alpha"]
     sigma = K * kappa ** 0.5 * float(mp.re(it["sigma1"]))
-    g, l = A.coexistence(A.EOS_CS, T_R)
+    g, l = A.coexistence(A.EOS_CS, T_r)
     radii = (32, 48, 64, 96)
     ps, r0 = [], []
     for R in radii:
         n = int(8 * ((2 * R + 12 * W) // 8 + 1))
-        ps.append(lbm.params(lbm.EOS_CS, T_R, n, n, kappa=kappa, tau=1.0, k=K))
+        ps.append(lbm.params(lbm.EOS_CS, T_r, n, n, kappa=kappa, tau=1.0, k=K))
         r0.append(inputs.droplet(n, n, g, l, R, W)[0])
     b = lbm.Batch(ps, r0)
     _converge(b, len(radii))
     inv_r, dp = [], []
+    print("\nT/Tc %.2f:  R0  equimolar R  rho_in   rho_out     k^2 dp0     k^2 dp0 R" % T_r)
     for i, p in enumerate(ps):
         r = b.moments(i)[0]
         n = p.nx
@@ -83,9 +113,11 @@ def test_drops_follow_laplaces_law():
         req = float(np.sqrt((r - rout).sum() / (np.pi * (rin - rout))))  # equimolar radius
         inv_r.append(1.0 / req)
         dp.append(K * K * float(mp.re(e.p0(mp.mpf(rin), T, al) - e.p0(mp.mpf(rout), T, al))))
+        print("           %3d  %7.2f    %.5f  %.4e  %.4e  %.2e" % (
+            radii[i], req, rin, rout, dp[-1], dp[-1] * req))
     jump_r = np.array(dp) / np.array(inv_r)  # sigma implied by each drop
-    print("\nLaplace: dP R = %s (continuum sigma %.4e)" % (
-        " ".join("%.4e" % v for v in jump_r), sigma), flush=True)
+    print("Laplace: dP R = %s (continuum sigma %.4e, ratio %.2f)" % (
+        " ".join("%.4e" % v for v in jump_r), sigma, jump_r.mean() / sigma), flush=True)
     assert np.all(np.diff(dp) < 0)                 # smaller drops, larger jump
     assert (jump_r.max() - jump_r.min()) <= 0.03 * jump_r.mean()
     assert 1.3 < jump_r.mean() / sigma < 2.0
