@@ -162,7 +162,7 @@ def sweep_bench(lbm, inputs, which):
 # training drops converged by the solver, then unseen drops run from the tanh
 # start and from the warm start to the same criterion.
 WARM = {"small": dict(train=96, train_n=128, eval=8, eval_n=128),
-        "full": dict(train=192, train_n=256, eval=8, eval_n=512)}
+        "full": dict(train=192, train_n=256, eval=32, eval_n=512)}
 
 
 def warmstart_bench(which):
