@@ -450,14 +450,26 @@ void set_row_shape(KParams *p)
 
 void set_col_shape(KParams *p, int width, int chunk)
 {
-    int wmax = kMaxBlockElems / p->ny;
-    if (wmax < 1) wmax = 1;
-    int w = width < 1 ? 1 : (width > wmax ? wmax : width);
-    p->cols_per_block = w;
-    p->col_threads = round_threads(w * p->ny);
     p->col_lc = chunk;
     iir_carry(*p, chunk, &p->iir_m_col, &p->iir_qL_col);
-    p->use_iir_cols = (chunk == 4 || chunk == 8 || chunk == 16) && iir_cols_ok(*p, chunk, w);
+    // the factorised solve holds up to kMaxColElems nodes of a strip (one
+    // thread per chunk, at most kMaxBlockThreads); the general reduction
+    // kernel kMaxBlockElems
+    int w = width < 1 ? 1 : width;
+    const bool fast = chunk == 4 || chunk == 8 || chunk == 16;
+    int wmax = fast ? kMaxColElems / p->ny : 0;
+    if (fast && kMaxBlockThreads * chunk / p->ny < wmax) wmax = kMaxBlockThreads * chunk / p->ny;
+    if (wmax >= 1 && iir_cols_ok(*p, chunk, w < wmax ? w : wmax)) {
+        w = w < wmax ? w : wmax;
+        p->use_iir_cols = 1;
+    } else {
+        wmax = kMaxBlockElems / p->ny;
+        if (wmax < 1) wmax = 1;
+        w = w < wmax ? w : wmax;
+        p->use_iir_cols = 0;
+    }
+    p->cols_per_block = w;
+    p->col_threads = round_threads(w * p->ny);
     const int nb = col_blocks(*p);
     p->col_xcd_groups = (nb % 8 == 0 && nb >= 64 && p->nx % w == 0) ? 8 : 1;
 }

@@ -841,7 +841,7 @@ bool iir_cols_ok(const KParams &p, int lc, int width)
 {
     return p.ny >= kFastMinLine && p.ny % lc == 0 && p.ny / lc > kCarry(lc) &&
            p.iir_m_col <= kCarry(lc) && width * (p.ny / lc) <= kMaxBlockThreads &&
-           width * p.ny <= kMaxBlockElems;
+           width * p.ny <= kMaxColElems;
 }
 
 static size_t row_lds_iir(const KParams &p, bool collide)

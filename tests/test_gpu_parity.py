@@ -107,17 +107,18 @@ def test_general_reduction_path(walls):
     _run_case("general98x66-walls%d" % walls, p, op, rho0, ux0, uy0, [50, 200])
 
 
-@pytest.mark.parametrize("walls", [0, 1])
-def test_every_column_shape_matches_oracle(walls):
+@pytest.mark.parametrize("walls,nx,ny", [(0, 128, 256), (1, 128, 256), (1, 64, 2048)])
+def test_every_column_shape_matches_oracle(walls, nx, ny):
     """Every column-pass shape the autotuner may pick (strip width x chunk
     length, chunk 0 = general reduction kernel) gives mu and F within 1e-12
-    of the oracle on the same state; the tuned choice too."""
-    nx, ny = 128, 256
+    of the oracle on the same state; the tuned choice too.  The 2048-node
+    columns take strips of up to 8192 nodes (4 columns) with 8- and 16-node
+    chunks."""
     p, op = _case_params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls)
     g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 30.0, 4.0, seed=12, noise=1e-4,
-                                    center=(60.0, 120.0))
+                                    center=(nx * 0.47, ny * 0.47))
     f = oracle.init(op, rho0, ux0, uy0)
     _, _, _, mu2, fx2, fy2 = oracle.moments(op, f, want_force=True)
     fm = max(np.abs(fx2).max(), np.abs(fy2).max())
@@ -136,9 +137,9 @@ def test_every_column_shape_matches_oracle(walls):
         assert np.abs(mu - mu2).max() <= 1e-12 * np.abs(mu2).max()
         assert np.abs(fy - fy2).max() <= 1e-12 * fm
         assert np.abs(fx - fx2).max() <= 1e-12 * fm
-    assert tried >= 10
+    assert tried >= (10 if ny <= 256 else 6)
     table = s.autotune(3)
-    assert len(table) >= 10
+    assert len(table) >= (10 if ny <= 256 else 6)
     mu, fx, fy = s.force_fields()
     assert np.abs(fy - fy2).max() <= 1e-12 * fm
 
