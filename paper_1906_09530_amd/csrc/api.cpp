@@ -835,7 +835,18 @@ lbm_status batch_upload(lbm_batch *b)
     for (int s : order) {
         const KParams &k = b->kp[s];
         for (int y0 = 0; y0 < k.ny; y0 += k.rows_per_block) rows.push_back({s, y0});
-        for (int x0 = 0; x0 < k.nx; x0 += k.cols_per_block) cols.push_back({s, x0});
+        // Workgroups go to the 8 XCDs round-robin by index.  Where a mesh's
+        // strips start at a multiple of 8 and number a multiple of 8 (64 or
+        // more), XCD g gets the contiguous strips [g S/8, (g+1) S/8), so that
+        // neighbouring strips, which share cache lines, share an L2.
+        const int S = (k.nx + k.cols_per_block - 1) / k.cols_per_block;
+        if (cols.size() % 8 == 0 && S % 8 == 0 && S >= 64) {
+            const int per = S / 8;
+            for (int i = 0; i < S; ++i)
+                cols.push_back({s, ((i % 8) * per + i / 8) * k.cols_per_block});
+        } else {
+            for (int x0 = 0; x0 < k.nx; x0 += k.cols_per_block) cols.push_back({s, x0});
+        }
     }
     b->n_rows = (int)rows.size();
     b->n_cols = (int)cols.size();
