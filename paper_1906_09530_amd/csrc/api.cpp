@@ -228,6 +228,9 @@ void carve(lbm_ctx *c, int red_blocks)
     c->red = (double *)m;
 }
 
+// One step = pass A, pass B, pass C.  The first observation plane doubles as
+// the F_x scratch of the split collision pass: the observation planes are
+// only written by calls that run between steps on the same stream.
 lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
 {
     for (int64_t s = 0; s < n; ++s) {
