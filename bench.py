@@ -443,6 +443,8 @@ def main():
         "kernels": {PASS_NAMES[i]: {"avg_ms": round(pass_ms[i], 6), "GB_s": round(gbs[i], 1),
                                     "bytes_per_node": PASS_BYTES[i]} for i in range(3)},
         "step_algorithmic_GB_s": round(sum(PASS_BYTES) * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
+        # MLUPS x 144 B (f read and written once: the floor of any scheme)
+        "floor_equivalent_GB_s": round(144 * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
         "autotune_col_width_ms": {str(k): round(v, 6) for k, v in tune.items()},
         "wall_s": round(wall, 3),
         "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
