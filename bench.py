@@ -400,6 +400,7 @@ def main():
     s.close()
 
     traffic = measured_traffic(PASS_NAMES[dom])
+    step_traffic = [measured_traffic(n) for n in PASS_NAMES]
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
     warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)
     splash = None if args.splash == "none" else splash_bench(torch, lbm, inputs)
@@ -445,6 +446,10 @@ def main():
         "step_algorithmic_GB_s": round(sum(PASS_BYTES) * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
         # MLUPS x 144 B (f read and written once: the floor of any scheme)
         "floor_equivalent_GB_s": round(144 * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
+        # HBM bytes of the three passes (FETCH_SIZE + WRITE_SIZE per launch,
+        # committed profile) over the step time
+        "step_measured_GB_s": (None if None in step_traffic else
+                               round(sum(step_traffic) / (ms_per_step * 1e-3) / 1e9, 1)),
         "autotune_col_width_ms": {str(k): round(v, 6) for k, v in tune.items()},
         "wall_s": round(wall, 3),
         "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
