@@ -176,10 +176,17 @@ def warmstart_bench(which):
     net, losses, secs = warmstart.train_network(x, t)
     log("  trained in %.1f s (final loss %.3e)" % (secs, float(losses[-20:].mean())))
     # radii of the unseen drops drawn from the training drops' range
+    # BF16 inference (the network's deployed precision) and FP32 beside it
     res = warmstart.compare(net, 55, cfg["eval"], cfg["eval_n"], 1e-12, 100, 3_000_000, log=log,
-                            bf16=False, r_scale=cfg["train_n"] / cfg["eval_n"])
+                            modes=(True, False), r_scale=cfg["train_n"] / cfg["eval_n"])
     net.close()
     st, sw = sum(res["steps_tanh"]), sum(res["steps_warm"])
+    other = {k: {"steps_warm": sum(v["steps_warm"]),
+                 "steps_ratio": round(sum(v["steps_warm"]) / st, 4),
+                 "seconds_warm": v["seconds_warm"], "fallbacks": v["fallbacks"],
+                 "all_converged": all(x == 0 for x in v["status_warm"]),
+                 "max_rel_drho_vs_tanh_solution": v["max_rel_drho"]}
+             for k, v in res["by_inference"].items()}
     return {
         "set": which, "training": info, "samples": int(len(t)), "train_s": round(secs, 2),
         "eval_drops": cfg["eval"], "eval_n": cfg["eval_n"],
@@ -193,6 +200,7 @@ def warmstart_bench(which):
         "fallbacks": res["fallbacks"],
         "max_rel_drho_vs_tanh_solution": res["max_rel_drho"],
         "max_abs_dv_vs_tanh_solution": res["max_abs_dv"],
+        "by_inference": other,
     }
 
 

@@ -156,7 +156,8 @@ def train_network(x, t, *, seed=11, phases=((6000, 2e-3), (6000, 4e-4)), batch=4
     return net, losses, secs
 
 
-def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_scale=1.0):
+def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_scale=1.0,
+            modes=None):
     """Unseen drops at n x n from the tanh start (Eq. 41, zero velocity) and
     from the warm start (same mass, predicted density and fluid velocity),
     run to the same criterion; the tanh start with the fluid at rest is run
@@ -165,8 +166,11 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
     times (the warm start's includes building its fields) and the largest
     differences between the converged states of the two starts.  r_scale
     scales the drawn radii (to keep a larger mesh's drops within the radii the
-    network was trained on)."""
+    network was trained on).  modes: inference precisions to evaluate (bf16
+    flags, default [bf16]); the tanh runs are shared, the top-level results
+    are those of the first mode and "by_inference" holds every mode's."""
     import torch
+    modes = [bf16] if modes is None else list(modes)
     members = inputs.warmstart_members(seed, count, **RANGES)
     plist = [drop_params(m, n) for m in members]
     radii = [r_scale * m["r_frac"] * n for m in members]
@@ -175,36 +179,44 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
     br, steps_r, _, _ = converge(plist, tanh0, tol, every, max_steps, log,
                                  [(None, None)] * count)
     br.close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rho0, v0, fallback = [], [], 0
-    for p, R, r in zip(plist, radii, tanh0):
-        try:
-            rho, vx, vy = net.warm_start_drop(p, R, float(r.sum()), bf16=bf16)
-            rho0.append(rho)
-            v0.append((vx, vy))
-        except lbm.LBMError:
-            rho0.append(r)
-            v0.append(None)
-            fallback += 1
-    torch.cuda.synchronize()
-    secs_ws = time.perf_counter() - t0
-    bw, steps_w, sts_w, secs_w = converge(plist, rho0, tol, every, max_steps, log, v0)
-    drho, dv = [], []
-    for i in range(len(plist)):
-        r1, vx1, vy1 = bt.moments(i)
-        r2, vx2, vy2 = bw.moments(i)
-        drho.append(float(np.abs(r1 - r2).max() / r1.max()))
-        dv.append(float(max(np.abs(vx1 - vx2).max(), np.abs(vy1 - vy2).max())))
-    mass = [float(abs(_host(w).sum() - r.sum()) / r.sum()) for w, r in zip(rho0, tanh0)]
+    by = {}
+    for mode in modes:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho0, v0, fallback = [], [], 0
+        for p, R, r in zip(plist, radii, tanh0):
+            try:
+                rho, vx, vy = net.warm_start_drop(p, R, float(r.sum()), bf16=mode)
+                rho0.append(rho)
+                v0.append((vx, vy))
+            except lbm.LBMError:
+                rho0.append(r)
+                v0.append(None)
+                fallback += 1
+        torch.cuda.synchronize()
+        secs_ws = time.perf_counter() - t0
+        bw, steps_w, sts_w, secs_w = converge(plist, rho0, tol, every, max_steps, log, v0)
+        drho, dv = [], []
+        for i in range(len(plist)):
+            r1, vx1, vy1 = bt.moments(i)
+            r2, vx2, vy2 = bw.moments(i)
+            drho.append(float(np.abs(r1 - r2).max() / r1.max()))
+            dv.append(float(max(np.abs(vx1 - vx2).max(), np.abs(vy1 - vy2).max())))
+        mass = [float(abs(_host(w).sum() - r.sum()) / r.sum()) for w, r in zip(rho0, tanh0)]
+        bw.close()
+        by["bf16" if mode else "fp32"] = {
+            "steps_warm": steps_w, "status_warm": sts_w, "fallbacks": fallback,
+            "seconds_warm": round(secs_w + secs_ws, 3), "seconds_warm_fields": round(secs_ws, 4),
+            "max_rel_drho": max(drho), "max_abs_dv": max(dv), "max_rel_mass_gap": max(mass),
+        }
     bt.close()
-    bw.close()
-    return {
+    first = by["bf16" if modes[0] else "fp32"]
+    out = {
         "drops": count, "n": n, "tol": tol, "check_every": every,
-        "inference": "bf16" if bf16 else "fp32",
-        "steps_tanh": steps_t, "steps_warm": steps_w, "steps_tanh_at_rest": steps_r,
-        "status_tanh": sts_t, "status_warm": sts_w, "fallbacks": fallback,
-        "seconds_tanh": round(secs_t, 3), "seconds_warm": round(secs_w + secs_ws, 3),
-        "seconds_warm_fields": round(secs_ws, 4),
-        "max_rel_drho": max(drho), "max_abs_dv": max(dv), "max_rel_mass_gap": max(mass),
+        "inference": "bf16" if modes[0] else "fp32",
+        "steps_tanh": steps_t, "steps_tanh_at_rest": steps_r, "status_tanh": sts_t,
+        "seconds_tanh": round(secs_t, 3),
     }
+    out.update(first)
+    out["by_inference"] = by
+    return out

@@ -183,11 +183,12 @@ def test_trained_warm_start_converges_in_fewer_steps_to_the_same_fields():
     net, losses, secs = warmstart.train_network(x, t)
     print("training: loss %.3e -> %.3e in %.2f s" % (losses[:20].mean(), losses[-20:].mean(),
                                                     secs), flush=True)
-    for bf16 in (True, False):
-        res = warmstart.compare(net, 55, 6, 128, 1e-12, 100, 400_000, bf16=bf16)
-        print("comparison: %s" % res, flush=True)
-        assert all(s == lbm.LBM_OK for s in res["status_tanh"] + res["status_warm"])
+    res = warmstart.compare(net, 55, 6, 128, 1e-12, 100, 400_000, modes=(True, False))
+    print("comparison: %s" % res, flush=True)
+    assert all(s == lbm.LBM_OK for s in res["status_tanh"])
+    for mode, r in res["by_inference"].items():
+        assert all(s == lbm.LBM_OK for s in r["status_warm"]), mode
         # measured: 210,700 (FP32) vs 256,600 steps from the tanh start
-        assert sum(res["steps_warm"]) < 0.9 * sum(res["steps_tanh"])
-    assert res["max_rel_mass_gap"] <= 1e-13
-    assert res["max_rel_drho"] <= 1e-8 and res["max_abs_dv"] <= 1e-8
+        assert sum(r["steps_warm"]) < 0.9 * sum(res["steps_tanh"]), mode
+        assert r["max_rel_mass_gap"] <= 1e-13
+        assert r["max_rel_drho"] <= 1e-8 and r["max_abs_dv"] <= 1e-8
