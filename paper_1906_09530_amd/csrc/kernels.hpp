@@ -9,8 +9,8 @@ constexpr int kMaxStages = 8;        // parallel cyclic reduction stages
 constexpr int kElemsPerThread = 4;   // line elements held by one thread
 constexpr int kMaxBlockThreads = 1024;
 constexpr int kMaxBlockElems = kMaxBlockThreads * kElemsPerThread;  // 4096 doubles per LDS buffer
-// nodes of a column strip the factorised solve holds (values, ghosts and
-// carries take at most ~98 KB of the 160 KB of LDS)
+// nodes of a column strip the factorised solve holds (one thread per chunk;
+// its LDS, four edge values and two carries per chunk, stays under ~50 KB)
 constexpr int kMaxColElems = 8192;
 constexpr int kFastMinLine = 64;     // lines this long skip the general modulo indexing
 

@@ -40,7 +40,9 @@ constexpr int kCarry(int lc) { return lc == 4 ? 11 : (lc == 8 ? 6 : 3); }
 
 // The thread's chunk within the block's lines, and the LDS layout of a
 // block's line solves:
-//   values  n + 4 per line: the line with two ghost nodes at each end;
+//   edges   4 (nc + 2) per line: each chunk's first two and last two values
+//           (all the right-hand side needs of a neighbour), with a ghost
+//           chunk before the first and after the last;
 //   cP, cB  nc + kCarry(LC) per line: one carry per chunk, with kCarry ghost
 //           chunks before the first (cP) or after the last (cB).
 // The ghosts hold the periodic images, or at walls the reflected values, so
@@ -57,10 +59,11 @@ struct Chunk {
     bool mirror;
     int l, c;   // this thread's line and chunk
     bool ok;    // the line exists (ragged last block)
-    // value j in [-2, n + 2)
-    __device__ __forceinline__ int vslot(int j) const
+    // edge value e of chunk ci in [-1, nc]: e = 0, 1 its first two nodes,
+    // e = 2, 3 its last two
+    __device__ __forceinline__ int eslot(int ci, int e) const
     {
-        return col ? (j + 2) * nl + l : l * (n + 4) + j + 2;
+        return col ? ((ci + 1) * 4 + e) * nl + l : l * 4 * (nc + 2) + (ci + 1) * 4 + e;
     }
     // cP of chunk ci in [-MC, nc), cB of chunk ci in [0, nc + MC)
     __device__ __forceinline__ int pslot(int ci) const
@@ -83,7 +86,7 @@ __device__ __forceinline__ LineLds carve_lds(double *smem, const Chunk<LC> &m)
 {
     LineLds L;
     L.vbuf = smem;
-    L.cP = smem + (size_t)m.nl * (m.n + 4);
+    L.cP = smem + (size_t)m.nl * 4 * (m.nc + 2);
     L.cB = L.cP + (size_t)m.nl * (m.nc + Chunk<LC>::MC);
     L.edge = L.cB + (size_t)m.nl * (m.nc + Chunk<LC>::MC);
     return L;
@@ -98,28 +101,30 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
 {
     constexpr int MC = Chunk<LC>::MC;
     double *vbuf = L.vbuf, *cP = L.cP, *cB = L.cB;
-    const int j0 = m.c * LC, n = m.n, nc = m.nc;
+    const int c = m.c, nc = m.nc;
     if (m.ok) {
-#pragma unroll
-        for (int k = 0; k < LC; ++k) vbuf[m.vslot(j0 + k)] = u[k];
-        // ghost nodes: periodic images, or the even (par_u = 1) or odd
+        vbuf[m.eslot(c, 0)] = u[0];
+        vbuf[m.eslot(c, 1)] = u[1];
+        vbuf[m.eslot(c, 2)] = u[LC - 2];
+        vbuf[m.eslot(c, 3)] = u[LC - 1];
+        // ghost chunks: periodic images, or the even (par_u = 1) or odd
         // (par_u = -1) reflection about the wall half a node past the end
-        if (m.c == 0) {
+        if (c == 0) {
             if (m.mirror) {
-                vbuf[m.vslot(-2)] = par_u * u[1];
-                vbuf[m.vslot(-1)] = par_u * u[0];
+                vbuf[m.eslot(-1, 2)] = par_u * u[1];
+                vbuf[m.eslot(-1, 3)] = par_u * u[0];
             } else {
-                vbuf[m.vslot(n)] = u[0];
-                vbuf[m.vslot(n + 1)] = u[1];
+                vbuf[m.eslot(nc, 0)] = u[0];
+                vbuf[m.eslot(nc, 1)] = u[1];
             }
         }
-        if (m.c == nc - 1) {
+        if (c == nc - 1) {
             if (m.mirror) {
-                vbuf[m.vslot(n)] = par_u * u[LC - 1];
-                vbuf[m.vslot(n + 1)] = par_u * u[LC - 2];
+                vbuf[m.eslot(nc, 0)] = par_u * u[LC - 1];
+                vbuf[m.eslot(nc, 1)] = par_u * u[LC - 2];
             } else {
-                vbuf[m.vslot(-2)] = u[LC - 2];
-                vbuf[m.vslot(-1)] = u[LC - 1];
+                vbuf[m.eslot(-1, 2)] = u[LC - 2];
+                vbuf[m.eslot(-1, 3)] = u[LC - 1];
             }
         }
     }
@@ -127,9 +132,10 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
     const double q = p.iir_q;
     double r[LC], y[LC], z[LC];
     if (m.ok) {
-        // u at j0-2, j0-1, j0+LC, j0+LC+1
-        const double um2 = vbuf[m.vslot(j0 - 2)], um1 = vbuf[m.vslot(j0 - 1)];
-        const double up0 = vbuf[m.vslot(j0 + LC)], up1 = vbuf[m.vslot(j0 + LC + 1)];
+        // u at j0-2, j0-1 (end of the previous chunk), j0+LC, j0+LC+1 (start
+        // of the next)
+        const double um2 = vbuf[m.eslot(c - 1, 2)], um1 = vbuf[m.eslot(c - 1, 3)];
+        const double up0 = vbuf[m.eslot(c + 1, 0)], up1 = vbuf[m.eslot(c + 1, 1)];
         auto U = [&](int i) -> double {
             return i == -2 ? um2 : i == -1 ? um1 : i == LC ? up0 : i == LC + 1 ? up1 : u[i];
         };
@@ -783,7 +789,7 @@ __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict
 static size_t line_lds(int n, int nl, int lc, bool edges)
 {
     const size_t nc = n / lc, L = nl;
-    return sizeof(double) * (L * (n + 4) + 2 * L * (nc + kCarry(lc)) + (edges ? 6 * L * nc : 0));
+    return sizeof(double) * (L * 4 * (nc + 2) + 2 * L * (nc + kCarry(lc)) + (edges ? 6 * L * nc : 0));
 }
 
 size_t batch_row_lds(int rows, int nx, bool collide) { return line_lds(nx, rows, kRowLC, collide); }
@@ -792,8 +798,8 @@ size_t batch_row_lds(int rows, int nx, bool collide) { return line_lds(nx, rows,
 size_t batch_col_lds(int col_elems, int lc, int wmax)
 {
     const size_t W = wmax;
-    return sizeof(double) *
-           ((size_t)col_elems + 4 * W + 2 * ((size_t)col_elems / lc + W * kCarry(lc)));
+    return sizeof(double) * (4 * ((size_t)col_elems / lc + 2 * W) +
+                             2 * ((size_t)col_elems / lc + W * kCarry(lc)));
 }
 
 hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
