@@ -181,9 +181,10 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, dou
  *   0  one kernel over whole rows, reading the populations twice;
  *   1  one kernel over whole rows holding the populations in registers
  *      (rows of at most 1024 nodes; the default there);
- *   2  split for long rows (at least 2048 nodes, a multiple of 1024): F_x
- *      over whole rows from the density and mu planes, then the collision
- *      over 1024-node row segments holding the populations in registers.
+ *   2  split for long rows (more than 1024 nodes, dividing into equal
+ *      segments of at most 1024 nodes in 4-node chunks): F_x over whole rows
+ *      from the density and mu planes, then the collision over the row
+ *      segments holding the populations in registers.
  *      F_x then takes rho from pass A (the sum of the density groups)
  *      instead of the collision's own sum of f, so results differ from
  *      variants 0 and 1 in the last bits.

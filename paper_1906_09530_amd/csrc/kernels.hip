@@ -444,7 +444,10 @@ void set_row_shape(KParams *p)
     p->rows_per_block = R;
     p->row_threads = round_threads(R * p->nx);
     p->use_iir_rows = iir_rows_ok(*p);
-    p->seg_len = kSegLen;
+    // split collision pass: the fewest equal segments of at most kSegLen
+    // nodes, each a whole number of 4-node chunks (0: not available)
+    const int nseg = (p->nx + kSegLen - 1) / kSegLen;
+    p->seg_len = (p->nx % nseg == 0 && (p->nx / nseg) % kIirRowChunk == 0) ? p->nx / nseg : 0;
     p->row_split = 0;
 }
 

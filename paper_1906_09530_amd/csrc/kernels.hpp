@@ -35,14 +35,14 @@ struct KParams {
     int use_iir_rows, use_iir_cols, col_lc;
     int row_keep;   // collision pass holds f in registers (tuned)
     int row_split;  // collision pass split for long rows (tuned; see below)
-    int seg_len;    // row segment of the split collision pass
+    int seg_len;    // row segment of the split collision pass (0: none)
     int iir_m_row, iir_m_col;
     double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
     double iir_qp[17];
 };
 
 constexpr int kIirRowChunk = 4;
-constexpr int kSegLen = 1024;  // nodes per segment of the split collision pass
+constexpr int kSegLen = 1024;  // longest segment of the split collision pass
 
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
@@ -131,9 +131,10 @@ hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const doub
                                    const double *fy, double *fout, double *gout, double *o_rho,
                                    double *o_vx, double *o_vy, double *o_fx, bool observe,
                                    hipStream_t s);
-// Split collision pass for rows of at least 2 kSegLen nodes in whole
-// segments: F_x over whole rows into fx (N doubles of scratch, from the rho
-// and mu planes), then the collision over row segments into (fout, gout).
+// Split collision pass for rows longer than kSegLen nodes that divide into
+// equal segments (seg_len) of at most kSegLen nodes in 4-node chunks: F_x
+// over whole rows into fx (N doubles of scratch, from the rho and mu planes),
+// then the collision over row segments into (fout, gout).
 bool iir_split_ok(const KParams &p);
 hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
                                     const double *mu, const double *fy, double *fx,

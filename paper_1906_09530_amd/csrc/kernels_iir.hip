@@ -674,10 +674,10 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
 // ---- split collision pass for long rows -------------------------------
 // Rows longer than one 256-thread workgroup holds with the populations in
 // registers run pass C as two kernels: the row derivatives and F_x over whole
-// rows (k_rows_fx_iir), then the collision without a line solve over
-// 1024-node row segments in 256-thread workgroups that hold f in registers
-// (k_collide_seg_iir); k_group_seams then forms the density groups of the
-// segments' end nodes from the finished f.
+// rows (k_rows_fx_iir), then the collision without a line solve over equal
+// row segments of at most 1024 nodes (seg_len) in workgroups of at most 256
+// threads that hold f in registers (k_collide_seg_iir); k_group_seams then
+// forms the density groups of the segments' end nodes from the finished f.
 
 // F_x = -rho d/dx mu + c_s^2 d/dx rho (Eq. 12) from the rho and mu planes.
 __device__ __forceinline__ void rows_fx_body(const KParams &p, int y0,
@@ -897,30 +897,31 @@ hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double 
 
 bool iir_split_ok(const KParams &p)
 {
-    return p.use_iir_rows && p.nx >= 2 * kSegLen && p.nx % kSegLen == 0;
+    return p.use_iir_rows && p.nx > kSegLen && p.seg_len > 0 && p.nx % p.seg_len == 0 &&
+           p.seg_len % kRowLC == 0 && p.seg_len <= kSegLen && p.nx / p.seg_len >= 2;
 }
 
 hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
                                     const double *mu, const double *fy, double *fx,
                                     double *fout, double *gout, hipStream_t s)
 {
-    if (!iir_split_ok(p) || p.seg_len != kSegLen) return hipErrorInvalidValue;
+    if (!iir_split_ok(p)) return hipErrorInvalidValue;
     const int T = row_threads_iir(p);
 #define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, rho, mu, fx
     CPLBM_IIR_THREADS(T, k_rows_fx_iir<256>, k_rows_fx_iir<1024>, ARGS);
 #undef ARGS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int blocks = p.ny * (p.nx / kSegLen);
-    const size_t lds = line_lds(kSegLen, 1, kRowLC, true);
+    const int S = p.seg_len, blocks = p.ny * (p.nx / S);
+    const size_t lds = line_lds(S, 1, kRowLC, true);
     if (p.row_keep)
-        hipLaunchKernelGGL(k_collide_seg_iir<true>, dim3(blocks), dim3(kSegLen / kRowLC), lds, s,
+        hipLaunchKernelGGL(k_collide_seg_iir<true>, dim3(blocks), dim3(S / kRowLC), lds, s,
                            p, f, fy, fx, fout, gout);
     else
-        hipLaunchKernelGGL(k_collide_seg_iir<false>, dim3(blocks), dim3(kSegLen / kRowLC), lds, s,
+        hipLaunchKernelGGL(k_collide_seg_iir<false>, dim3(blocks), dim3(S / kRowLC), lds, s,
                            p, f, fy, fx, fout, gout);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t seams = (size_t)p.ny * (p.nx / kSegLen) * 2;
+    const size_t seams = (size_t)p.ny * (p.nx / S) * 2;
     hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
                        (const double *)fout, gout);
     return hipGetLastError();

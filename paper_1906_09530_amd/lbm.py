@@ -247,7 +247,8 @@ class Solver:
 
     def set_collision_variant(self, variant):
         """0: one pass reading f twice; 1: one pass, f in registers; 2: split
-        for rows of >= 2048 nodes (derivative pass + segmented collision)."""
+        for rows of more than 1024 nodes (derivative pass + collision over
+        equal row segments of at most 1024 nodes)."""
         _check(load().lbm_set_collision_variant(self.ctx, int(variant)), self.ctx)
 
     def set_column_shape(self, width, chunk):

@@ -408,11 +408,13 @@ def test_other_equations_of_state(eos):
     _run_case("eos%d" % eos, p, op, rho0, ux0, uy0, [100, 300])
 
 
-@pytest.mark.parametrize("nx,ny,walls", [(2048, 48, 0), (3072, 40, 1)])
+@pytest.mark.parametrize("nx,ny,walls", [(2048, 48, 0), (3072, 40, 1), (1536, 40, 1),
+                                         (3000, 32, 0)])
 def test_split_collision_for_long_rows(nx, ny, walls):
     """The split collision variant (F_x over whole rows, then the collision
-    over 1024-node row segments, then the density groups of the segments'
-    end nodes): parity with the oracle after 100 and 200 steps; a run resumed
+    over equal row segments of at most 1024 nodes -- 1024, 1024, 768 and 1000
+    here -- then the density groups of the segments' end nodes): parity with
+    the oracle after 100 and 200 steps; a run resumed
     from its own state ends bitwise where the uninterrupted one does (the
     groups formed at the seams equal those of f); and the whole-row variant
     agrees to round-off."""
