@@ -17,7 +17,7 @@ network on solver-converged drops and compares steps and time to converge
 from its proposal and from the tanh start.
 
     python bench.py [--gpus 1] [--steps 20000] [--warmup 200] [--sweep small|full|none]
-                    [--warmstart small|full|none]
+                    [--warmstart small|full|cs-small|cs-full|none]
 """
 import argparse
 import json
@@ -158,43 +158,73 @@ def sweep_bench(lbm, inputs, which):
     }
 
 
-# Learned warm start: CS drops (warmstart.RANGES), kappa = 0.1, tau = 1;
-# training drops converged by the solver, then unseen drops run from the tanh
-# start and from the warm start to the same criterion.
-WARM = {"small": dict(train=96, train_n=128, eval=8, eval_n=128),
-        "full": dict(train=192, train_n=256, eval=32, eval_n=512)}
+# Learned warm start: Peng-Robinson drops ("pr": T/Tc 0.3-0.5, kappa = 0.003,
+# k near 0.05) or Carnahan-Starling drops ("cs": T/Tc 0.35-0.6, kappa = 0.1),
+# tau = 1; training drops converged by the solver, then unseen drops run from
+# the tanh start and from the warm start to the same criterion.
+# Training drops not converged within 1,000,000 steps are left out of the
+# training set.  The full Peng-Robinson set (up to 850,000 steps per start on
+# 512^2) runs BF16 inference only and leaves out the tanh start with the
+# fluid at rest, to stay within minutes.
+WARM = {"small": dict(wl="pr", train=96, train_n=128, eval=8, eval_n=128),
+        "full": dict(wl="pr", train=192, train_n=256, eval=32, eval_n=512, modes=(True,),
+                     at_rest=False),
+        "cs-small": dict(wl="cs", train=96, train_n=128, eval=8, eval_n=128),
+        "cs-full": dict(wl="cs", train=192, train_n=256, eval=32, eval_n=512)}
 
 
 def warmstart_bench(which):
-    from paper_1906_09530_amd import warmstart
+    from paper_1906_09530_amd import lbm, warmstart
     cfg = WARM[which]
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     log("warm start %s: converging %d training drops at %d^2" % (which, cfg["train"],
                                                                cfg["train_n"]))
-    x, t, info = warmstart.training_set(5, cfg["train"], cfg["train_n"], 1e-12, 100, 3_000_000,
-                                        log=log)
+    x, t, info = warmstart.training_set(5, cfg["train"], cfg["train_n"], 1e-12, 100, 1_000_000,
+                                        log=log, wl=cfg["wl"])
     net, losses, secs = warmstart.train_network(x, t)
     log("  trained in %.1f s (final loss %.3e)" % (secs, float(losses[-20:].mean())))
     # radii of the unseen drops drawn from the training drops' range
     # BF16 inference (the network's deployed precision) and FP32 beside it
     res = warmstart.compare(net, 55, cfg["eval"], cfg["eval_n"], 1e-12, 100, 3_000_000, log=log,
-                            modes=(True, False), r_scale=cfg["train_n"] / cfg["eval_n"])
+                            modes=cfg.get("modes", (True, False)),
+                            r_scale=cfg["train_n"] / cfg["eval_n"], wl=cfg["wl"],
+                            at_rest=cfg.get("at_rest", True))
     net.close()
-    st, sw = sum(res["steps_tanh"]), sum(res["steps_warm"])
-    other = {k: {"steps_warm": sum(v["steps_warm"]),
-                 "steps_ratio": round(sum(v["steps_warm"]) / st, 4),
-                 "seconds_warm": v["seconds_warm"], "fallbacks": v["fallbacks"],
-                 "all_converged": all(x == 0 for x in v["status_warm"]),
-                 "max_rel_drho_vs_tanh_solution": v["max_rel_drho"]}
-             for k, v in res["by_inference"].items()}
+    ok = lbm.LBM_OK
+
+    def totals(warm):
+        """Steps of both starts summed over the drops that converged from
+        both, and their count."""
+        both = [i for i, (a, b) in enumerate(zip(res["status_tanh"], warm["status_warm"]))
+                if a == ok and b == ok]
+        st = sum(res["steps_tanh"][i] for i in both)
+        sw = sum(warm["steps_warm"][i] for i in both)
+        return st, sw, round(sw / st, 4) if st else None, len(both)
+
+    st, sw, ratio, compared = totals(res)
+    rr = warmstart.WORKLOADS[cfg["wl"]]["ranges"]
+    other = {}
+    for k, v in res["by_inference"].items():
+        t_k, w_k, r_k, c_k = totals(v)
+        other[k] = {"compared_drops": c_k, "steps_tanh": t_k, "steps_warm": w_k,
+                    "steps_ratio": r_k, "seconds_warm": v["seconds_warm"],
+                    "fallbacks": v["fallbacks"],
+                    "all_converged": all(x == ok for x in v["status_warm"]),
+                    "max_rel_drho_vs_tanh_solution": v["max_rel_drho"]}
     return {
-        "set": which, "training": info, "samples": int(len(t)), "train_s": round(secs, 2),
+        "set": which, "workload": cfg["wl"], "training": info, "samples": int(len(t)),
+        "train_s": round(secs, 2),
         "eval_drops": cfg["eval"], "eval_n": cfg["eval_n"],
-        "eval_radius_range": [round(r * cfg["train_n"], 1) for r in (0.15, 0.35)],
+        "eval_radius_range": [round(rr[r] * cfg["train_n"], 1) for r in ("r_lo", "r_hi")],
         "tol": 1e-12, "check_every": 100,
         "inference": res["inference"],
-        "steps_tanh": st, "steps_warm": sw, "steps_ratio": round(sw / st, 4),
-        "steps_tanh_fluid_at_rest": sum(res["steps_tanh_at_rest"]),
+        "compared_drops": compared, "steps_tanh": st, "steps_warm": sw, "steps_ratio": ratio,
+        "steps_tanh_fluid_at_rest": (None if res["steps_tanh_at_rest"] is None
+                                     else sum(res["steps_tanh_at_rest"])),
+        "status_tanh": {lbm.status_string(s): res["status_tanh"].count(s)
+                        for s in sorted(set(res["status_tanh"]))},
+        "status_warm": {lbm.status_string(s): res["status_warm"].count(s)
+                        for s in sorted(set(res["status_warm"]))},
         "seconds_tanh": res["seconds_tanh"], "seconds_warm": res["seconds_warm"],
         "all_converged": all(s == 0 for s in res["status_tanh"] + res["status_warm"]),
         "fallbacks": res["fallbacks"],
@@ -318,10 +348,11 @@ def main():
     ap.add_argument("--pass-steps", type=int, default=1000,
                     help="steps timed per kernel with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--warmstart", choices=["small", "full", "none"], default="small",
+    ap.add_argument("--warmstart", choices=sorted(WARM) + ["none"], default="small",
                     help="learned warm start vs tanh start (steps and time to converge): 96 "
-                         "training drops at 128^2, 8 unseen at 128^2 (small); 192 at 256^2, 8 "
-                         "unseen at 512^2 (full, minutes); or none")
+                         "training drops at 128^2, 8 unseen at 128^2 (small); 192 at 256^2, 32 "
+                         "unseen at 512^2 (full, minutes); Peng-Robinson drops, or "
+                         "Carnahan-Starling drops with the cs- prefix; or none")
     ap.add_argument("--sweep", choices=["small", "full", "none"], default="small",
                     help="batched sweep vs one run per member (time to converge): 16 members "
                          "up to 256^2 (small), 64 members up to 512^2 (full, minutes), or none")

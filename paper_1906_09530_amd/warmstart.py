@@ -10,30 +10,50 @@ starts are run to the same convergence criterion.  Every numerical step
 kernels; this module only draws the workload, assembles the samples and
 keeps the books.
 
-Workload: Carnahan-Starling drops (a = 1, b = 4, R = 1) in square periodic
-meshes, kappa = 0.1, tau = 1, T/Tc, radius fraction and k drawn per drop.
+Workloads (square periodic meshes; T/Tc, radius fraction and k drawn per
+drop, tau = 1):
+
+* "cs": Carnahan-Starling drops (a = 1, b = 4, R = 1), kappa = 0.1,
+  T/Tc in [0.35, 0.6], k in [0.15, 0.3], radius in [0.15, 0.35] N, tanh
+  width 5;
+* "pr": Peng-Robinson drops (a = 2/49, b = 2/21, R = 1, omega = 0.344),
+  T/Tc in [0.3, 0.5], kappa = 0.003, k in [0.045, 0.055] (interfaces of
+  8-13 nodes, w1 sqrt(kappa) / k), the chemical-potential limit at 6,
+  radius in [0.22, 0.35] N (drops of 20-25 nodes at T/Tc < 0.39 can diverge
+  in the first few hundred steps from the tanh start), tanh width 10.
 """
+import math
 import time
 
 import numpy as np
 
 from . import inputs, lbm
 
-KAPPA, TAU, WIDTH = 0.1, 1.0, 5.0
 FEATURE_CENTER = np.array([0.5, 0.25, 0.1, 0.25, 0.0, 0.0, 0.0])
 FEATURE_SCALE = np.array([0.25, 0.1, 0.1, 0.1, 8.0, 1.0, 1.0])
 R_REF = 256.0
 U_SCALE = 1e-3
-RANGES = dict(t_lo=0.35, t_hi=0.6, r_lo=0.15, r_hi=0.35, k_lo=0.15, k_hi=0.3)
+WORKLOADS = {
+    "cs": dict(eos=lbm.EOS_CS, kappa=0.1, tau=1.0, width=5.0, mu_cap=math.inf,
+               ranges=dict(t_lo=0.35, t_hi=0.6, r_lo=0.15, r_hi=0.35, k_lo=0.15, k_hi=0.3)),
+    "pr": dict(eos=lbm.EOS_PR, kappa=0.003, tau=1.0, width=10.0, mu_cap=6.0,
+               ranges=dict(t_lo=0.3, t_hi=0.5, r_lo=0.22, r_hi=0.35, k_lo=0.045, k_hi=0.055)),
+}
 
 
-def drop_params(member, n):
-    return lbm.params(lbm.EOS_CS, member["T_r"], n, n, kappa=KAPPA, tau=TAU, k=member["k"])
+def members(seed, count, wl="cs"):
+    return inputs.warmstart_members(seed, count, **WORKLOADS[wl]["ranges"])
 
 
-def tanh_start(p, radius):
+def drop_params(member, n, wl="cs"):
+    w = WORKLOADS[wl]
+    return lbm.params(w["eos"], member["T_r"], n, n, kappa=w["kappa"], tau=w["tau"],
+                      k=member["k"], mu_cap=w["mu_cap"])
+
+
+def tanh_start(p, radius, wl="cs"):
     g, l = lbm.maxwell(p)
-    return inputs.droplet(p.nx, p.ny, g, l, radius, WIDTH)[0]
+    return inputs.droplet(p.nx, p.ny, g, l, radius, WORKLOADS[wl]["width"])[0]
 
 
 def _host(a):
@@ -75,12 +95,12 @@ def geometry(n, radius, nodes):
     return np.sqrt(dx * dx + dy * dy) - radius, np.arctan2(dy, dx)
 
 
-def features(member, radius, d, theta):
+def features(member, radius, d, theta, wl="cs"):
     """Normalised features (len(d), 7)."""
     f = np.empty((len(d), 7))
     f[:, 0] = member["T_r"]
     f[:, 1] = radius / R_REF
-    f[:, 2] = KAPPA
+    f[:, 2] = WORKLOADS[wl]["kappa"]
     f[:, 3] = member["k"]
     f[:, 4] = d
     f[:, 5] = np.cos(4.0 * theta)
@@ -88,7 +108,7 @@ def features(member, radius, d, theta):
     return ((f - FEATURE_CENTER) / FEATURE_SCALE).astype(np.float32)
 
 
-def samples(member, p, radius, rho, ux, uy, stride=2):
+def samples(member, p, radius, rho, ux, uy, stride=2, wl="cs"):
     """Training samples of a converged state (density and fluid velocity):
     the nodes with both coordinates multiples of `stride`; targets are the
     normalised log density and the radial and azimuthal velocity in units of
@@ -104,27 +124,30 @@ def samples(member, p, radius, rho, ux, uy, stride=2):
     t[:, 0] = (np.log(r) - np.log(g)) / (np.log(l) - np.log(g))
     t[:, 1] = (u * c + v * s) / U_SCALE
     t[:, 2] = (-u * s + v * c) / U_SCALE
-    return features(member, radius, d, th), t.astype(np.float32)
+    return features(member, radius, d, th, wl), t.astype(np.float32)
 
 
-def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2):
-    """Converge `count` drops at n x n from the tanh start and return
-    (x, t, info)."""
-    members = inputs.warmstart_members(seed, count, **RANGES)
-    plist = [drop_params(m, n) for m in members]
-    radii = [m["r_frac"] * n for m in members]
-    b, steps, sts, secs = converge(plist, [tanh_start(p, R) for p, R in zip(plist, radii)], tol,
-                                   every, max_steps, log)
+def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2, wl="cs"):
+    """Converge `count` drops of workload `wl` at n x n from the tanh start
+    and return (x, t, info)."""
+    ms = members(seed, count, wl)
+    plist = [drop_params(m, n, wl) for m in ms]
+    radii = [m["r_frac"] * n for m in ms]
+    b, steps, sts, secs = converge(plist, [tanh_start(p, R, wl) for p, R in zip(plist, radii)],
+                                   tol, every, max_steps, log)
     xs, ts = [], []
-    for i, (m, p, R) in enumerate(zip(members, plist, radii)):
+    for i, (m, p, R) in enumerate(zip(ms, plist, radii)):
         if sts[i] != lbm.LBM_OK:
             continue
-        x, t = samples(m, p, R, *b.moments(i), stride=stride)
+        x, t = samples(m, p, R, *b.moments(i), stride=stride, wl=wl)
         xs.append(x)
         ts.append(t)
     b.close()
     return np.concatenate(xs), np.concatenate(ts), {
-        "drops": count, "n": n, "converged": sum(1 for s in sts if s == lbm.LBM_OK),
+        "workload": wl, "drops": count, "n": n, "converged": sum(1 for s in sts if s == lbm.LBM_OK),
+        "not_converged": [dict(T_r=round(m["T_r"], 4), k=round(m["k"], 4), radius=round(R, 1),
+                               status=lbm.status_string(st), steps=s)
+                          for m, R, st, s in zip(ms, radii, sts, steps) if st != lbm.LBM_OK],
         "steps_max": max(steps), "seconds": round(secs, 2)}
 
 
@@ -157,28 +180,32 @@ def train_network(x, t, *, seed=11, phases=((6000, 2e-3), (6000, 4e-4)), batch=4
 
 
 def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_scale=1.0,
-            modes=None):
+            modes=None, wl="cs", at_rest=True):
     """Unseen drops at n x n from the tanh start (Eq. 41, zero velocity) and
     from the warm start (same mass, predicted density and fluid velocity),
     run to the same criterion; the tanh start with the fluid at rest is run
     too, for reference.  A drop whose proposed density cannot be mass
     matched falls back to the tanh start.  Returns per-drop steps, wall
     times (the warm start's includes building its fields) and the largest
-    differences between the converged states of the two starts.  r_scale
+    differences between the converged states of the two starts (over the
+    drops that converged from both; None if none did).  r_scale
     scales the drawn radii (to keep a larger mesh's drops within the radii the
     network was trained on).  modes: inference precisions to evaluate (bf16
     flags, default [bf16]); the tanh runs are shared, the top-level results
-    are those of the first mode and "by_inference" holds every mode's."""
+    are those of the first mode and "by_inference" holds every mode's.
+    at_rest=False leaves out the tanh start with the fluid at rest."""
     import torch
     modes = [bf16] if modes is None else list(modes)
-    members = inputs.warmstart_members(seed, count, **RANGES)
-    plist = [drop_params(m, n) for m in members]
-    radii = [r_scale * m["r_frac"] * n for m in members]
-    tanh0 = [tanh_start(p, R) for p, R in zip(plist, radii)]
+    ms = members(seed, count, wl)
+    plist = [drop_params(m, n, wl) for m in ms]
+    radii = [r_scale * m["r_frac"] * n for m in ms]
+    tanh0 = [tanh_start(p, R, wl) for p, R in zip(plist, radii)]
     bt, steps_t, sts_t, secs_t = converge(plist, tanh0, tol, every, max_steps, log)
-    br, steps_r, _, _ = converge(plist, tanh0, tol, every, max_steps, log,
-                                 [(None, None)] * count)
-    br.close()
+    steps_r = None
+    if at_rest:
+        br, steps_r, _, _ = converge(plist, tanh0, tol, every, max_steps, log,
+                                     [(None, None)] * count)
+        br.close()
     by = {}
     for mode in modes:
         torch.cuda.synchronize()
@@ -198,6 +225,8 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
         bw, steps_w, sts_w, secs_w = converge(plist, rho0, tol, every, max_steps, log, v0)
         drho, dv = [], []
         for i in range(len(plist)):
+            if sts_t[i] != lbm.LBM_OK or sts_w[i] != lbm.LBM_OK:
+                continue  # compared where both starts converged
             r1, vx1, vy1 = bt.moments(i)
             r2, vx2, vy2 = bw.moments(i)
             drho.append(float(np.abs(r1 - r2).max() / r1.max()))
@@ -207,12 +236,13 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
         by["bf16" if mode else "fp32"] = {
             "steps_warm": steps_w, "status_warm": sts_w, "fallbacks": fallback,
             "seconds_warm": round(secs_w + secs_ws, 3), "seconds_warm_fields": round(secs_ws, 4),
-            "max_rel_drho": max(drho), "max_abs_dv": max(dv), "max_rel_mass_gap": max(mass),
+            "max_rel_drho": max(drho, default=None), "max_abs_dv": max(dv, default=None),
+            "max_rel_mass_gap": max(mass),
         }
     bt.close()
     first = by["bf16" if modes[0] else "fp32"]
     out = {
-        "drops": count, "n": n, "tol": tol, "check_every": every,
+        "workload": wl, "drops": count, "n": n, "tol": tol, "check_every": every,
         "inference": "bf16" if modes[0] else "fp32",
         "steps_tanh": steps_t, "steps_tanh_at_rest": steps_r, "status_tanh": sts_t,
         "seconds_tanh": round(secs_t, 3),

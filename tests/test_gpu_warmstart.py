@@ -172,23 +172,30 @@ def test_warm_start_of_a_centred_drop_is_mirror_symmetric():
     assert np.abs(ux).max() > 1e-5
 
 
-def test_trained_warm_start_converges_in_fewer_steps_to_the_same_fields():
+# (workload, training drops that must converge within 400,000 steps)
+TRAINED = [("cs", 96), ("pr", 94)]
+
+
+@pytest.mark.parametrize("wl,min_converged", TRAINED)
+def test_trained_warm_start_converges_in_fewer_steps_to_the_same_fields(wl, min_converged):
     """96 drops at 128^2 converged by the solver train the network; 6 unseen
     drops then run from the tanh start and from the warm start (density and
     fluid velocity) to max |drho| < 1e-12 per 100 steps, and end in the same
-    state."""
-    x, t, info = warmstart.training_set(5, 96, 128, 1e-12, 100, 400_000, log=print)
+    state.  Carnahan-Starling drops at T/Tc 0.35-0.6 and Peng-Robinson drops
+    at T/Tc 0.3-0.5 (one of whose training drops keeps oscillating above the
+    criterion; training uses the converged ones)."""
+    x, t, info = warmstart.training_set(5, 96, 128, 1e-12, 100, 400_000, log=print, wl=wl)
     print("\ntraining set: %s, %d samples" % (info, len(t)), flush=True)
-    assert info["converged"] == 96
+    assert info["converged"] >= min_converged
     net, losses, secs = warmstart.train_network(x, t)
     print("training: loss %.3e -> %.3e in %.2f s" % (losses[:20].mean(), losses[-20:].mean(),
                                                     secs), flush=True)
-    res = warmstart.compare(net, 55, 6, 128, 1e-12, 100, 400_000, modes=(True, False))
+    res = warmstart.compare(net, 55, 6, 128, 1e-12, 100, 400_000, modes=(True, False), wl=wl)
     print("comparison: %s" % res, flush=True)
     assert all(s == lbm.LBM_OK for s in res["status_tanh"])
     for mode, r in res["by_inference"].items():
         assert all(s == lbm.LBM_OK for s in r["status_warm"]), mode
-        # measured: 210,700 (FP32) vs 256,600 steps from the tanh start
+        # measured, CS: 210,700 (FP32) vs 256,600 steps from the tanh start
         assert sum(r["steps_warm"]) < 0.9 * sum(res["steps_tanh"]), mode
         assert r["max_rel_mass_gap"] <= 1e-13
         assert r["max_rel_drho"] <= 1e-8 and r["max_abs_dv"] <= 1e-8
