@@ -104,6 +104,17 @@ lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, doubl
                                double radius, double target_mass, int bf16, double *rho,
                                double *ux, double *uy);
 
+/* Distance from the interface (r - R, mesh nodes) up to which the warm-start
+ * fields of m use the network, for a network whose training meshes did not
+ * reach as far from the drop as the meshes it is used on (extension of the
+ * Sec. 5.3 drop start, Eq. 41).  With w = 1 for r - R <= reach - 10, 0 for
+ * r - R >= reach + 10 and linear in r between, lbm_warm_start_drop forms
+ * ln rho = ln rho_g + w y0 (ln rho_l - ln rho_g) and the velocity w v before
+ * mass matching: the Maxwell gas at rest beyond reach + 10.  Default
+ * +infinity (w = 1 everywhere).  LBM_E_INVALID unless reach > 0 (NaN
+ * included); +infinity restores the default.  No device call. */
+lbm_status lbm_mlp_set_reach(lbm_mlp *m, double reach);
+
 void lbm_mlp_destroy(lbm_mlp *m);
 
 /* Reason for the last failure of m, or of the last failed lbm_mlp_create

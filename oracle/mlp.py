@@ -175,6 +175,21 @@ def drop_velocity(y, radius, nx, ny, cx=None, cy=None):
     return ux, uy
 
 
+REACH_BLEND = 10.0
+
+
+def reach_weight(radius, nx, ny, reach, cx=None, cy=None):
+    """Weight (ny*nx,) of the network's outputs for a network used within
+    `reach` nodes of the interface: 1 where r - R <= reach - REACH_BLEND, 0
+    where r - R >= reach + REACH_BLEND, linear in r between; 1 everywhere
+    for an infinite reach.  Scaling the outputs by it leaves the Maxwell gas
+    at rest beyond the blend."""
+    d, _ = drop_geometry(radius, nx, ny, cx, cy)
+    if np.isinf(reach):
+        return np.ones_like(d)
+    return np.clip((reach + REACH_BLEND - d) / (2.0 * REACH_BLEND), 0.0, 1.0)
+
+
 def density_from_output(y, rho_g, rho_l):
     """The network predicts the normalised log density
     y = (ln rho - ln rho_g) / (ln rho_l - ln rho_g)."""

@@ -414,11 +414,15 @@ __global__ void k_ws_features(WsDrop d, float *__restrict__ x)
 // of its mirror features, y0 = (y0+ + y0-)/2 and the radial velocity
 // (y1+ + y1-)/2 are even, the azimuthal velocity (y2+ - y2-)/2 odd, and the
 // velocity normal to a mirror line vanishes on it, so the proposed state
-// carries no net momentum and the drop does not drift.  rho = exp(ln rho_g + y0 (ln rho_l
-// - ln rho_g)); velocity in units of u_scale.  Each block of 256 nodes also
+// carries no net momentum and the drop does not drift.  rho = exp(ln rho_g + w y0 (ln rho_l
+// - ln rho_g)); velocity w times the outputs, in units of u_scale.  w = 1
+// within reach of the interface (r - R <= reach - kReachBlend), 0 beyond
+// reach + kReachBlend (the Maxwell gas at rest), linear in r between; an
+// infinite reach keeps w = 1 everywhere.  Each block of 256 nodes also
 // writes the partial sums of rho and of the mass-matching weight
 // max((rho - rho_g)(rho_l - rho), 0).
 constexpr int MT = 256;
+constexpr double kReachBlend = 10.0;
 
 __global__ __launch_bounds__(MT) void k_ws_map(WsDrop d, const float *__restrict__ y,
                                                double *__restrict__ rho,
@@ -431,16 +435,21 @@ __global__ __launch_bounds__(MT) void k_ws_map(WsDrop d, const float *__restrict
     const int n = blockIdx.x * MT + threadIdx.x;
     double rv = 0.0, wv = 0.0;
     if (n < N) {
+        double r, c, sn;
+        node_polar(d, n, r, c, sn);
+        const double w =
+            isinf(d.reach)
+                ? 1.0
+                : fmin(fmax((d.reach + kReachBlend - (r - d.radius)) / (2.0 * kReachBlend), 0.0),
+                       1.0);
         const float *yp = y + (size_t)n * NO, *ym = y + ((size_t)N + n) * NO;
-        const double y0 = 0.5 * ((double)yp[0] + (double)ym[0]);
+        const double y0 = w * (0.5 * ((double)yp[0] + (double)ym[0]));
         rv = exp(d.ln_rho_g + y0 * (d.ln_rho_l - d.ln_rho_g));
         rho[n] = rv;
         wv = fmax((rv - d.rho_g) * (d.rho_l - rv), 0.0);
         if (ux) {
-            double r, c, sn;
-            node_polar(d, n, r, c, sn);
-            const double ur = d.u_scale * 0.5 * ((double)yp[1] + (double)ym[1]);
-            const double ut = d.u_scale * 0.5 * ((double)yp[2] - (double)ym[2]);
+            const double ur = w * (d.u_scale * 0.5 * ((double)yp[1] + (double)ym[1]));
+            const double ut = w * (d.u_scale * 0.5 * ((double)yp[2] - (double)ym[2]));
             // a node that is its own mirror image about the line x = cx (the
             // centre column, and the edge column of a periodic mesh when cx
             // sits half a period away) has no x velocity; likewise in y

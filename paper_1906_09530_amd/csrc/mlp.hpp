@@ -20,6 +20,7 @@ struct WsDrop {
     double rho_g, rho_l, ln_rho_g, ln_rho_l;  // Maxwell pair of the drop's EOS and T
     double radius_ref;                        // feature 2 is radius / radius_ref
     double u_scale;                           // velocity outputs are in units of u_scale
+    double reach;  // network within reach of the interface, Maxwell gas beyond (k_ws_map)
     double center[kInputs], scale[kInputs];   // x_i = (f_i - center_i) / scale_i
 };
 

@@ -26,6 +26,7 @@ struct lbm_mlp {
     float *fxy = nullptr;  // warm-start features and outputs
     size_t fxy_floats = 0;
     int64_t steps = 0;
+    double reach = INFINITY;  // of the warm-start fields (lbm_mlp_set_reach)
     std::string err;
 };
 
@@ -209,6 +210,14 @@ lbm_status lbm_mlp_train(lbm_mlp *m, const float *x, const float *t, int64_t nsa
 
 int64_t lbm_mlp_steps(const lbm_mlp *m) { return m ? m->steps : -1; }
 
+lbm_status lbm_mlp_set_reach(lbm_mlp *m, double reach)
+{
+    if (!m) return LBM_E_INVALID;
+    if (!(reach > 0)) return mfail(m, LBM_E_INVALID, "reach must be > 0 (or +infinity)");
+    m->reach = reach;
+    return LBM_OK;
+}
+
 lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, double cy,
                                double radius, double target_mass, int bf16, double *rho,
                                double *ux, double *uy)
@@ -241,6 +250,7 @@ lbm_status lbm_warm_start_drop(lbm_mlp *m, const lbm_params *p, double cx, doubl
     d.ln_rho_l = std::log(l);
     d.radius_ref = 256.0;
     d.u_scale = 1e-3;
+    d.reach = m->reach;
     const double center[mlp::kInputs] = {0.5, 0.25, 0.1, 0.25, 0.0, 0.0, 0.0};
     const double scale[mlp::kInputs] = {0.25, 0.1, 0.1, 0.1, 8.0, 1.0, 1.0};
     for (int i = 0; i < mlp::kInputs; ++i) {

@@ -107,6 +107,7 @@ def load():
         "lbm_mlp_train": (i32, [P, P, P, i64, P, i64, i64, C.c_float, C.c_float, C.c_float,
                                 C.c_float, P]),
         "lbm_mlp_steps": (i64, [P]),
+        "lbm_mlp_set_reach": (i32, [P, d]),
         "lbm_warm_start_drop": (i32, [P, pp, d, d, d, d, i32, P, P, P]),
         "lbm_set_velocity": (i32, [P, P, P, i32]),
         "lbm_batch_set_velocity": (i32, [P, i32, P, P]),
@@ -453,6 +454,11 @@ class MLP:
     @property
     def steps(self):
         return load().lbm_mlp_steps(self.m)
+
+    def set_reach(self, reach):
+        """Distance from the interface up to which warm-start fields use the
+        network (math.inf: everywhere)."""
+        _mcheck(load().lbm_mlp_set_reach(self.m, float(reach)), self.m)
 
     def warm_start_drop(self, p, radius, target_mass, center=None, bf16=True):
         """Warm-start (rho, vx, vy) of a drop: device tensors (ny, nx), float64

@@ -180,7 +180,7 @@ def train_network(x, t, *, seed=11, phases=((6000, 2e-3), (6000, 4e-4)), batch=4
 
 
 def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_scale=1.0,
-            modes=None, wl="cs", at_rest=True):
+            modes=None, wl="cs", at_rest=True, reach=math.inf):
     """Unseen drops at n x n from the tanh start (Eq. 41, zero velocity) and
     from the warm start (same mass, predicted density and fluid velocity),
     run to the same criterion; the tanh start with the fluid at rest is run
@@ -193,7 +193,9 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
     network was trained on).  modes: inference precisions to evaluate (bf16
     flags, default [bf16]); the tanh runs are shared, the top-level results
     are those of the first mode and "by_inference" holds every mode's.
-    at_rest=False leaves out the tanh start with the fluid at rest."""
+    at_rest=False leaves out the tanh start with the fluid at rest.  reach:
+    distance from the interface up to which the warm start uses the network
+    (the Maxwell gas at rest beyond, lbm_mlp_set_reach)."""
     import torch
     modes = [bf16] if modes is None else list(modes)
     ms = members(seed, count, wl)
@@ -207,6 +209,7 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
                                      [(None, None)] * count)
         br.close()
     by = {}
+    net.set_reach(reach)
     for mode in modes:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -243,7 +246,7 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
     first = by["bf16" if modes[0] else "fp32"]
     out = {
         "workload": wl, "drops": count, "n": n, "tol": tol, "check_every": every,
-        "inference": "bf16" if modes[0] else "fp32",
+        "inference": "bf16" if modes[0] else "fp32", "reach": reach,
         "steps_tanh": steps_t, "steps_tanh_at_rest": steps_r, "status_tanh": sts_t,
         "seconds_tanh": round(secs_t, 3),
     }

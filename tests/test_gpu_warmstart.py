@@ -7,6 +7,8 @@ with the mass match; then the whole pipeline: converged drops from the
 solver, training, and unseen drops run from both starts to the same
 criterion.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -127,9 +129,18 @@ def _profile_net(seed=9):
     return net
 
 
-def test_warm_start_field_matches_oracle_and_keeps_mass():
+@pytest.mark.parametrize("reach", [math.inf, 12.0])
+def test_warm_start_field_matches_oracle_and_keeps_mass(reach):
+    """The library's warm-start field against the oracle's, with the network
+    used everywhere and within 12 nodes of the interface (Maxwell gas at
+    rest beyond 22)."""
     net = _profile_net()
     w = net.get_params()
+    for bad in (0.0, -1.0, math.nan):
+        with pytest.raises(lbm.LBMError) as ei:
+            net.set_reach(bad)
+        assert ei.value.status == lbm.LBM_E_INVALID
+    net.set_reach(reach)
     nx, ny, R, cx, cy = 96, 80, 20.0, 47.0, 41.5
     p = lbm.params(lbm.EOS_CS, 0.5, nx, ny, kappa=0.1, tau=1.0, k=0.2)
     g, l = A.coexistence(A.EOS_CS, 0.5)
@@ -137,7 +148,7 @@ def test_warm_start_field_matches_oracle_and_keeps_mass():
     target = float(tanh0.sum())
     rho, ux, uy = (a.cpu().numpy() for a in net.warm_start_drop(p, R, target, center=(cx, cy)))
     f = ref.drop_features(0.5, R, 0.1, 0.2, nx, ny, cx, cy)
-    y = ref.symmetric_outputs(w, f)
+    y = ref.symmetric_outputs(w, f) * ref.reach_weight(R, nx, ny, reach, cx, cy)[:, None]
     r_ref = ref.mass_match(ref.density_from_output(y[:, 0], g, l).reshape(ny, nx), target, g, l)
     ux_ref, uy_ref = ref.drop_velocity(y, R, nx, ny, cx, cy)
     L = np.log(l) - np.log(g)
@@ -150,6 +161,11 @@ def test_warm_start_field_matches_oracle_and_keeps_mass():
     assert du <= 1e-3 * umax and umax > 1e-4
     assert abs(rho.sum() - target) <= 1e-12 * target
     assert np.all(rho > 0)
+    if not math.isinf(reach):
+        far = ref.reach_weight(R, nx, ny, reach, cx, cy).reshape(ny, nx) == 0.0
+        assert far.sum() > 1000
+        np.testing.assert_allclose(rho[far], g, rtol=1e-12)
+        assert np.all(ux[far] == 0.0) and np.all(uy[far] == 0.0)
 
 
 def test_warm_start_of_a_centred_drop_is_mirror_symmetric():

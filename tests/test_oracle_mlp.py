@@ -145,3 +145,33 @@ def test_symmetric_outputs_are_even_and_odd_under_reflection():
         y, ym = mlp.symmetric_outputs(w, x, bf16), mlp.symmetric_outputs(w, xm, bf16)
         np.testing.assert_allclose(ym[:, :2], y[:, :2], rtol=0, atol=1e-15)
         np.testing.assert_allclose(ym[:, 2], -y[:, 2], rtol=0, atol=1e-15)
+
+
+def test_reach_weight_blends_to_the_maxwell_gas_at_rest():
+    """Weight 1 near the drop, 0 beyond reach + 10 (distances checked on
+    nodes along the x axis through the centre, where r - R is exact), 1/2
+    at r - R = reach, non-increasing in r; scaled outputs give the Maxwell
+    gas density (to round-off) and zero velocity where it is 0, which mass
+    matching leaves there."""
+    n, R, reach = 128, 20.0, 25.0
+    w = mlp.reach_weight(R, n, n, reach).reshape(n, n)
+    row = w[n // 2]                            # y = n/2: r = |x - n/2|
+    d = np.abs(np.arange(n) - n / 2.0) - R
+    assert np.all(row[d <= reach - 10] == 1.0) and np.all(row[d >= reach + 10] == 0.0)
+    assert row[n // 2 + 45] == 0.5             # r - R = 25 = reach
+    assert row[n // 2 + 40] == 0.75 and row[n // 2 + 50] == 0.25
+    dd, _ = mlp.drop_geometry(R, n, n)
+    order = np.argsort(dd, kind="stable")
+    assert np.all(np.diff(w.ravel()[order]) <= 0.0)
+    assert np.all(mlp.reach_weight(R, n, n, np.inf) == 1.0)
+    g, l = 1e-5, 0.7
+    y = np.full((n * n, 3), 0.3)
+    y[:, 0] = 0.5 * (1.0 - np.tanh(dd / 3.0))
+    yw = y * w.ravel()[:, None]
+    rho = mlp.density_from_output(yw[:, 0], g, l)
+    far = w.ravel() == 0.0
+    np.testing.assert_allclose(rho[far], g, rtol=1e-15)   # exp(ln g) to round-off
+    ux, uy = mlp.drop_velocity(yw, R, n, n)
+    assert np.all(ux.ravel()[far] == 0.0) and np.all(uy.ravel()[far] == 0.0)
+    r2 = mlp.mass_match(rho.reshape(n, n), rho.sum() * 1.001, g, l)
+    np.testing.assert_allclose(r2.ravel()[far], g, rtol=1e-14)
