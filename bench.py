@@ -238,6 +238,18 @@ def warmstart_bench(which):
     }
 
 
+def strict_json(obj):
+    """obj with every non-finite float replaced by None (None in the output
+    line stands for "not a number"), so the line is strict JSON."""
+    if isinstance(obj, float):
+        return obj if math.isfinite(obj) else None
+    if isinstance(obj, dict):
+        return {k: strict_json(v) for k, v in obj.items()}
+    if isinstance(obj, (list, tuple)):
+        return [strict_json(v) for v in obj]
+    return obj
+
+
 def copy_bandwidth(torch, nbytes, reps=20):
     """Read + write GB/s of the runtime's own device-to-device copy of
     nbytes / 2 (so that it moves nbytes per dispatch): the rate a plain
@@ -503,7 +515,7 @@ def main():
         "splash": splash,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(strict_json(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
