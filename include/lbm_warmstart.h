@@ -88,7 +88,8 @@ int64_t lbm_mlp_steps(const lbm_mlp *m);
 /* Warm-start fields of a static drop (radius, centre (cx, cy) in mesh
  * nodes) for the parameters p (periodic mesh, any EOS; features use p->T_r,
  * p->kappa, p->k), from the network (bf16 != 0: matrix-core inference, else
- * FP32): rho (device, ny*nx doubles, layout of lbm.h), mass matched --
+ * FP32; within the reach of lbm_mlp_set_reach, by default everywhere): rho
+ * (device, ny*nx doubles, layout of lbm.h), mass matched --
  * target_mass - sum(rho) is added in proportion to
  * max((rho - rho_g)(rho_l - rho), 0), which vanishes in both bulks, so that
  * sum(rho) = target_mass to round-off -- and the fluid velocity v (ux, uy:

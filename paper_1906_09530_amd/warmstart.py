@@ -195,7 +195,7 @@ def compare(net, seed, count, n, tol, every, max_steps, log=None, bf16=True, r_s
     are those of the first mode and "by_inference" holds every mode's.
     at_rest=False leaves out the tanh start with the fluid at rest.  reach:
     distance from the interface up to which the warm start uses the network
-    (the Maxwell gas at rest beyond, lbm_mlp_set_reach)."""
+    (the Maxwell gas at rest beyond, lbm_mlp_set_reach; net keeps it)."""
     import torch
     modes = [bf16] if modes is None else list(modes)
     ms = members(seed, count, wl)
