@@ -65,3 +65,13 @@ def test_warm_start_entry_compares_drops_that_converged_from_both(monkeypatch):
         assert out["status_warm"] == {"LBM_E_NONFINITE": 1, "LBM_OK": 3}
         assert out["all_converged"] is False
         assert out["by_inference"]["bf16"]["compared_drops"] == 2
+
+
+def test_cpu_baseline_times_the_oracle_on_the_bench_workload():
+    """The cpu_baseline leg: the oracle on the same 1024^2 PR drop, one
+    thread, at least one whole step within the budget."""
+    out = bench.cpu_baseline(budget_s=0.5)
+    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "MLUPS"
+    assert 0.0 < out["value"] < 1e3
+    assert "1024x1024 PR drop" in out["sample"]
+    json.dumps(out, allow_nan=False)
