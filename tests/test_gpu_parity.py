@@ -445,3 +445,26 @@ def test_split_collision_for_long_rows(nx, ny, walls):
     assert erc <= 1e-12 and evc <= 1e-10
     with pytest.raises(lbm.LBMError):
         lbm.Solver(p, rho0, ux0, uy0).set_collision_variant(1)   # rows need 1024 threads
+
+
+@pytest.mark.parametrize("cap", [6.0, 1.0, 0.5])
+def test_mu_limit_binds_at_seeded_nodes(cap):
+    """Sec. 5.6: the upper limit of psi' where it binds.  A 96 x 80 PR drop
+    at T_r = 0.6 with three liquid nodes seeded at 10.6 and 10.5 (at and
+    beyond 1/b = 10.5, outside the EOS domain, so the limit itself is used)
+    and 10.46 (inside the domain, psi' = 11.5 above the limit 6).  With the
+    limit at 6 it binds at the seeded nodes in the first step only; at 1.0
+    and 0.5 the start-up pressure waves push liquid nodes above the limit
+    (and beyond 1/b) during the first few hundred steps and the limit binds
+    at hundreds of nodes, then no more (oracle counts)."""
+    nx, ny = 96, 80
+    kw = dict(kappa=0.002, tau=0.8, k=0.1, mu_cap=cap)
+    p, op = _case_params(lbm.EOS_PR, 0.6, nx, ny, **kw)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 22.0, 5.0, seed=21, noise=1e-6)
+    rho0[40, 48], rho0[41, 49], rho0[38, 46] = 10.6, 10.5, 10.46
+    # the oracle's limit binds at the seeded nodes (and only there) at start
+    raw = A.params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1)
+    m = oracle.mu0_capped(raw, rho0.ravel())
+    assert (m >= cap).sum() >= 3
+    _run_case("pr-limit%g" % cap, p, op, rho0, ux0, uy0, [1, 20, 100, 300])
