@@ -198,6 +198,26 @@ lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
  * round-off. */
 lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Advances the state f[9][ny][nx] (device memory, caller-owned,
+ * the layout of lbm_get_state) by nsteps time steps in place, with the same
+ * kernels, pass shapes and results as lbm_init + lbm_step on a new context
+ * (no autotuning).  Every intermediate (the spare distribution buffer, the
+ * density groups, the scalar planes) lives in a static device array of
+ * 40 MiB that the library holds on each GPU it runs on until the process
+ * ends: the call allocates nothing.  Meshes of at most
+ * LBM_NOALLOC_MAX_NODES nodes; larger ones return LBM_E_INVALID before any
+ * work is enqueued.  The work is enqueued on hip_stream (NULL: the default
+ * stream) and the call returns without synchronising; the initial density
+ * is not checked (a non-finite result shows in f).  Every call on one GPU
+ * shares that GPU's array, so calls that overlap in time on one GPU (other
+ * streams, other host threads) race; calls on one stream are ordered.
+ * Errors: LBM_E_INVALID (parameters, size, NULL f, nsteps < 0),
+ * LBM_E_DEVICE (a HIP call failed), with the reason in lbm_last_error(NULL). */
+#define LBM_NOALLOC_MAX_NODES 262144
+lbm_status lbm_step_noalloc(const lbm_params *p, double *f, int64_t nsteps, void *hip_stream);
+
 /* Steps taken since lbm_init. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 

@@ -10,7 +10,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcplbm.so")
-SOURCES = ["kernels.hip", "kernels_iir.hip", "mlp.hip", "api.cpp", "mlp_api.cpp", "thermo.cpp"]
+SOURCES = ["kernels.hip", "kernels_iir.hip", "mlp.hip", "noalloc.hip", "api.cpp", "mlp_api.cpp",
+           "thermo.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -12,6 +12,7 @@
 
 #include "../../include/lbm.h"
 #include "kernels.hpp"
+#include "setup.hpp"
 #include "thermo.hpp"
 
 using namespace cplbm;
@@ -296,6 +297,20 @@ lbm_status enter(lbm_ctx *c)
 }
 
 }  // namespace
+
+namespace cplbm {
+
+lbm_status setup_params(const lbm_params *p, KParams *kp, std::string *why)
+{
+    lbm_status st = validate(p, why);
+    if (st != LBM_OK) return st;
+    if (!make_kparams(p, kp, why)) return LBM_E_INVALID;
+    return LBM_OK;
+}
+
+void set_global_error(const std::string &msg) { g_init_error = msg; }
+
+}  // namespace cplbm
 
 extern "C" {
 

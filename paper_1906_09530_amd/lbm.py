@@ -81,6 +81,7 @@ def load():
                             C.POINTER(C.c_int)]),
         "lbm_set_column_shape": (i32, [P, i32, i32]),
         "lbm_set_collision_variant": (i32, [P, i32]),
+        "lbm_step_noalloc": (i32, [pp, P, i64, P]),
         "lbm_steps_taken": (i64, [P]),
         "lbm_synchronize": (i32, [P]),
         "lbm_destroy": (None, [P]),
@@ -162,6 +163,16 @@ def _ptr(a):
         return a.data_ptr()
     assert isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data
+
+
+NOALLOC_MAX_NODES = 262144
+
+
+def step_noalloc(p, f, nsteps, stream=None):
+    """lbm_step_noalloc: advance the device state f (a float64 torch tensor of
+    9 * nx * ny, contiguous) by nsteps in place, with no device allocation."""
+    assert _is_device(f)
+    _check(load().lbm_step_noalloc(C.byref(p), _ptr(f), int(nsteps), stream), None)
 
 
 class Solver:

@@ -1,0 +1,70 @@
+"""lbm_step_noalloc against lbm_init + lbm_step on a new context.
+
+The allocation-free entry point keeps every intermediate in the library's
+static device array; it must give the context's result (same kernels, same
+default pass shapes) to the parity bar, on two calls in a row that share that
+array, the second on a smaller mesh, and reject a mesh beyond its limit
+before enqueuing any work.
+"""
+import numpy as np
+import pytest
+
+from oracle import analytic as A
+from paper_1906_09530_amd import inputs, lbm
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _context_result(p, rho0, nsteps):
+    """Initial state and the state after nsteps, both from a context."""
+    import torch
+    s = lbm.Solver(p, rho0)
+    f0 = torch.from_numpy(s.get_state()).cuda().contiguous()
+    s.step(nsteps)
+    f1 = s.get_state()
+    s.close()
+    return f0, f1
+
+
+def _compare(name, p, rho0, nsteps):
+    import torch
+    print("\n[case] %s nx=%d ny=%d steps=%d" % (name, p.nx, p.ny, nsteps), flush=True)
+    f0, ref = _context_result(p, rho0, nsteps)
+    f = f0.view(-1).clone()
+    torch.cuda.synchronize()
+    lbm.step_noalloc(p, f, nsteps)
+    torch.cuda.synchronize()
+    got = f.cpu().numpy().reshape(ref.shape)
+    assert np.isfinite(ref).all()
+    err = float(np.max(np.abs(got - ref) / np.abs(ref).max(axis=(1, 2), keepdims=True)))
+    print("  max rel err of f %.2e, bitwise %s" % (err, bool(np.array_equal(got, ref))),
+          flush=True)
+    assert err <= TOL
+    return got
+
+
+def test_noalloc_matches_context_on_two_calls():
+    # first call: 192 x 160 PR drop, odd step count (the result ends in the
+    # spare buffer and is copied back)
+    p1 = lbm.params(lbm.EOS_PR, 0.6, 192, 160, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0)
+    g, l = A.coexistence(lbm.EOS_PR, 0.6)
+    rho1, _, _ = inputs.droplet(192, 160, g, l, 40.0, 5.0, seed=31, noise=1e-6)
+    _compare("pr192x160", p1, rho1, 37)
+    # second call, smaller mesh between walls, even step count
+    p2 = lbm.params(lbm.EOS_CS, 0.6, 64, 96, kappa=0.1, tau=0.8, k=0.2, bc_y=1, wall_ux=0.01)
+    g2, l2 = A.coexistence(lbm.EOS_CS, 0.6)
+    rho2, _, _ = inputs.droplet(64, 96, g2, l2, 16.0, 4.0, seed=32, noise=1e-6)
+    _compare("cs64x96walls", p2, rho2, 20)
+
+
+def test_noalloc_rejects_meshes_beyond_its_limit():
+    import torch
+    p = lbm.params(lbm.EOS_CS, 0.6, 1024, 512, kappa=0.1, tau=0.8, k=0.2)
+    assert p.nx * p.ny > lbm.NOALLOC_MAX_NODES
+    f = torch.zeros(9 * 8, dtype=torch.float64, device="cuda")  # never touched
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.step_noalloc(p, f, 1)
+    assert ei.value.status == lbm.LBM_E_INVALID
+    assert "at most" in lbm.load().lbm_last_error(None).decode()
