@@ -46,6 +46,9 @@ typedef struct {
     double k;          /* proportional coefficient (Eq. 25) */
     double mu_cap;     /* upper limit of the bulk chemical potential (Sec. 5.6) */
     double cfd_alpha;  /* alpha of the compact scheme (Eqs. 37-39) */
+    int32_t collision; /* 0: BGK (Eq. 1); 1: MRT (Eq. 4) */
+    int32_t force;     /* 0: chemical potential (Eq. 12); 1: pseudopotential (Sec. 5.1) */
+    double s_e, s_eps, s_q;  /* MRT relaxation rates (Eq. 4); s_v = 1/tau */
 } orc_params;
 
 /* Temperature functions of the RK, RKS and PR EOS (Eqs. 16 and 18). */
@@ -232,6 +235,17 @@ static void cfm_cols2(const orc_params *p, const double *u, double *d2)
     free(dd);
 }
 
+/* Column derivative of a field as the step computes it: the first
+ * derivative (second = 0) or the scheme applied twice (second = 1), periodic
+ * in y or on the even extension between walls. */
+void orc_cfm_columns(const orc_params *p, const double *u, double *d, int second)
+{
+    if (second)
+        cfm_cols2(p, u, d);
+    else
+        cfm_cols(p, u, d);
+}
+
 /* ---- lattice Boltzmann pieces (Sec. 2) ---------------------------------- */
 
 /* Equilibrium of Eq. 2 with c_s^2 = 1/3. */
@@ -267,6 +281,87 @@ void orc_collide_node(const double *fi, double rho, double ux, double uy, double
     }
 }
 
+/* ---- multiple-relaxation-time collision (Eq. 4) -------------------------
+ * m = M f are the velocity moments of D2Q9 in the order the relaxation
+ * matrix S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, s_v, s_v) refers to:
+ * density rho, energy e, energy square eps, momentum j_x, energy flux q_x,
+ * j_y, q_y, and the stresses p_xx, p_xy.  Each row is a polynomial in the
+ * lattice velocity (e, eps and q from the orthogonalised powers of |e|^2):
+ *   1, 3|e|^2 - 4, (9|e|^4 - 21|e|^2 + 8)/2, e_x, (3|e|^2 - 5) e_x, e_y,
+ *   (3|e|^2 - 5) e_y, e_x^2 - e_y^2, e_x e_y. */
+void orc_mrt_matrix(double *M)
+{
+    for (int i = 0; i < 9; i++) {
+        double ex = EX[i], ey = EY[i], e2 = ex * ex + ey * ey;
+        double row[9] = {1.0,
+                         3.0 * e2 - 4.0,
+                         (9.0 * e2 * e2 - 21.0 * e2 + 8.0) / 2.0,
+                         ex,
+                         (3.0 * e2 - 5.0) * ex,
+                         ey,
+                         (3.0 * e2 - 5.0) * ey,
+                         ex * ex - ey * ey,
+                         ex * ey};
+        for (int k = 0; k < 9; k++) M[k * 9 + i] = row[k];
+    }
+}
+
+/* The rows of M are mutually orthogonal, so M^-1 = M^T diag(1 / |M_k|^2). */
+void orc_mrt_inverse(double *Minv)
+{
+    double M[81];
+    orc_mrt_matrix(M);
+    for (int k = 0; k < 9; k++) {
+        double n2 = 0.0;
+        for (int i = 0; i < 9; i++) n2 += M[k * 9 + i] * M[k * 9 + i];
+        for (int i = 0; i < 9; i++) Minv[i * 9 + k] = M[k * 9 + i] / n2;
+    }
+}
+
+/* Forced MRT collision at one node, Eq. 4 with the exact-difference force
+ * term of Eq. 5: f* = f - M^-1 S (m - m_eq) + feq(rho, u + F/rho) - feq(rho, u),
+ * with m_eq = M feq(rho, u) and S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau,
+ * 1/tau). */
+void orc_collide_node_mrt(const double *fi, double rho, double ux, double uy, double Fx,
+                          double Fy, double tau, double s_e, double s_eps, double s_q,
+                          double *fout)
+{
+    double M[81], Minv[81], eq[9], m[9], meq[9], dm[9];
+    double S[9] = {0.0, s_e, s_eps, 0.0, s_q, 0.0, s_q, 1.0 / tau, 1.0 / tau};
+    orc_mrt_matrix(M);
+    orc_mrt_inverse(Minv);
+    for (int i = 0; i < 9; i++) eq[i] = orc_feq(i, rho, ux, uy);
+    for (int k = 0; k < 9; k++) {
+        m[k] = 0.0;
+        meq[k] = 0.0;
+        for (int i = 0; i < 9; i++) {
+            m[k] += M[k * 9 + i] * fi[i];
+            meq[k] += M[k * 9 + i] * eq[i];
+        }
+        dm[k] = S[k] * (m[k] - meq[k]);
+    }
+    double dux = Fx / rho, duy = Fy / rho;
+    for (int i = 0; i < 9; i++) {
+        double back = 0.0;
+        for (int k = 0; k < 9; k++) back += Minv[i * 9 + k] * dm[k];
+        fout[i] = fi[i] - back + (orc_feq(i, rho, ux + dux, uy + duy) - eq[i]);
+    }
+}
+
+/* ---- pseudopotential comparison model (Sec. 5.1) -------------------------
+ * The Shan-Chen interaction force F = -G c_s^2 psi grad psi with G = -1 and
+ * the effective mass taken from the EOS, here the mesh pressure k^2 p0
+ * (Eq. 29): the force then carries the non-ideal part of that pressure,
+ * k^2 p0 = rho c_s^2 + G c_s^2 psi^2 / 2, so
+ * psi = sqrt(2 (rho c_s^2 - k^2 p0) / c_s^2) (0 where the argument is
+ * negative).  The gradient of psi comes from the same compact scheme. */
+double orc_sc_psi(const orc_params *p, double rho)
+{
+    double pr = p->k * p->k * orc_p0(p->eos, p->a, p->b, p->R, p->T, p->alpha_T, rho);
+    double arg = 2.0 * (rho * CS2 - pr) / CS2;
+    return arg > 0.0 ? sqrt(arg) : 0.0;
+}
+
 /* Scalar fields of one step, computed from the current f (Secs. 3-4):
  * rho, u, grad rho, the mesh chemical potential of Eq. 33 and the force of
  * Eq. 12.  Any output pointer may be NULL. */
@@ -288,6 +383,24 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
         double fi[9];
         for (int i = 0; i < 9; i++) fi[i] = f[(size_t)i * N + n];
         orc_node_moments(fi, &o->rho[n], &o->jx[n], &o->jy[n]);
+    }
+    if (p->force == 1) {
+        /* pseudopotential model: F = c_s^2 psi grad psi (G = -1); the mu
+         * output holds psi */
+        for (size_t n = 0; n < N; n++) o->mu[n] = orc_sc_psi(p, o->rho[n]);
+        cfm_rows(p, o->mu, dxm);
+        cfm_cols(p, o->mu, dym);
+        cfm_rows(p, o->rho, o->dxr);
+        cfm_cols(p, o->rho, o->dyr);
+        for (size_t n = 0; n < N; n++) {
+            o->fx[n] = CS2 * o->mu[n] * dxm[n];
+            o->fy[n] = CS2 * o->mu[n] * dym[n];
+        }
+        free(dxxr);
+        free(dyyr);
+        free(dxm);
+        free(dym);
+        return;
     }
     /* 2. density gradient and Laplacian by the compact scheme; the
      *    Laplacian is d/dx(d/dx rho) + d/dy(d/dy rho) (Sec. 4.3). */
@@ -365,8 +478,8 @@ void orc_init(const orc_params *p, const double *rho0, const double *ux0, const 
         for (int i = 0; i < 9; i++) f[(size_t)i * N + n] = orc_feq(i, rho0[n], ux0[n], uy0[n]);
 }
 
-/* One time step, Eq. 1: moments, chemical potential, force, collision,
- * streaming.  f is replaced by f(t+1). */
+/* One time step, Eq. 1 (or Eq. 4): moments, chemical potential, force,
+ * collision, streaming.  f is replaced by f(t+1). */
 void orc_step(const orc_params *p, double *f)
 {
     size_t N = (size_t)p->nx * p->ny;
@@ -377,8 +490,12 @@ void orc_step(const orc_params *p, double *f)
     for (size_t n = 0; n < N; n++) {
         double fi[9], fo[9];
         for (int i = 0; i < 9; i++) fi[i] = f[(size_t)i * N + n];
-        orc_collide_node(fi, o.rho[n], o.jx[n] / o.rho[n], o.jy[n] / o.rho[n], o.fx[n], o.fy[n],
-                         p->tau, fo);
+        if (p->collision == 1)
+            orc_collide_node_mrt(fi, o.rho[n], o.jx[n] / o.rho[n], o.jy[n] / o.rho[n], o.fx[n],
+                                 o.fy[n], p->tau, p->s_e, p->s_eps, p->s_q, fo);
+        else
+            orc_collide_node(fi, o.rho[n], o.jx[n] / o.rho[n], o.jy[n] / o.rho[n], o.fx[n],
+                             o.fy[n], p->tau, fo);
         for (int i = 0; i < 9; i++) fs[(size_t)i * N + n] = fo[i];
     }
     orc_stream(p, fs, o.rho, f);

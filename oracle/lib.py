@@ -22,7 +22,8 @@ class OracleParams(C.Structure):
         ("wall_ux", C.c_double), ("a", C.c_double), ("b", C.c_double), ("R", C.c_double),
         ("T", C.c_double), ("alpha_T", C.c_double), ("kappa", C.c_double),
         ("tau", C.c_double), ("k", C.c_double), ("mu_cap", C.c_double),
-        ("cfd_alpha", C.c_double),
+        ("cfd_alpha", C.c_double), ("collision", C.c_int32), ("force", C.c_int32),
+        ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
     ]
 
 
@@ -52,9 +53,14 @@ def load():
             ("orc_mu0", d, [i32, d, d, d, d, d, d]),
             ("orc_mu0_capped", d, [pp, d]),
             ("orc_cfm_line", None, [i32, d, P, P]),
+            ("orc_cfm_columns", None, [pp, P, P, i32]),
             ("orc_feq", d, [i32, d, d, d]),
             ("orc_node_moments", None, [P, P, P, P]),
             ("orc_collide_node", None, [P, d, d, d, d, d, d, P]),
+            ("orc_mrt_matrix", None, [P]),
+            ("orc_mrt_inverse", None, [P]),
+            ("orc_collide_node_mrt", None, [P, d, d, d, d, d, d, d, d, d, P]),
+            ("orc_sc_psi", d, [pp, d]),
             ("orc_stream", None, [pp, P, P, P]),
             ("orc_init", None, [pp, P, P, P, P]),
             ("orc_step", None, [pp, P]),
@@ -105,6 +111,15 @@ def cfm_line(u, alpha):
     return d
 
 
+def cfm_columns(p, u, second=False):
+    """d/dy (or the scheme applied twice) of the field u[ny][nx] as the
+    oracle's step takes it (even extension between walls)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    d = np.empty_like(u)
+    load().orc_cfm_columns(C.byref(p), _ptr(u), _ptr(d), int(second))
+    return d
+
+
 def feq(i, rho, ux, uy):
     return load().orc_feq(i, rho, ux, uy)
 
@@ -114,6 +129,30 @@ def collide_node(fi, rho, ux, uy, Fx, Fy, tau):
     out = np.empty(9)
     load().orc_collide_node(_ptr(fi), rho, ux, uy, Fx, Fy, tau, _ptr(out))
     return out
+
+
+def mrt_matrix():
+    M = np.empty((9, 9))
+    load().orc_mrt_matrix(_ptr(M))
+    return M
+
+
+def mrt_inverse():
+    M = np.empty((9, 9))
+    load().orc_mrt_inverse(_ptr(M))
+    return M
+
+
+def collide_node_mrt(fi, rho, ux, uy, Fx, Fy, tau, s_e, s_eps, s_q):
+    fi = np.ascontiguousarray(fi, dtype=np.float64)
+    out = np.empty(9)
+    load().orc_collide_node_mrt(_ptr(fi), rho, ux, uy, Fx, Fy, tau, s_e, s_eps, s_q, _ptr(out))
+    return out
+
+
+def sc_psi(p, rho):
+    f = load().orc_sc_psi
+    return np.vectorize(lambda r: f(C.byref(p), float(r)))(rho)
 
 
 def stream(p, fstar, rho):

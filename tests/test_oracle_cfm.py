@@ -101,3 +101,36 @@ def test_second_derivative_by_repetition():
         kp = (a * np.sin(th) + b / 2 * np.sin(2 * th)) / (1 + 2 * al * np.cos(th))
         d2 = oracle.cfm_line(oracle.cfm_line(np.cos(th * j), al), al)
         np.testing.assert_allclose(d2, -kp * kp * np.cos(th * j), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("al", [1 / 3, 1 / 4])
+@pytest.mark.parametrize("ny", [16, 40, 64])
+def test_wall_columns_closed_form(al, ny):
+    """Between walls (half a node beyond the first and last rows) a column is
+    differentiated on its even extension (the neighbour-node condition of
+    Sec. 5.5).  u(y) = cos(theta (y + 1/2)) with theta = pi m / ny is even
+    about both walls, so its extension is one Fourier mode of the 2 ny line:
+    the scheme returns exactly -k'(theta) sin(theta (y + 1/2)), and applied
+    twice -k'(theta)^2 u.  A mirror shifted by one node, or an odd extension,
+    breaks both."""
+    from oracle import analytic as A
+    a, b = 2 * (al + 2) / 3, (4 * al - 1) / 3
+    nx = 3
+    p = A.params(A.EOS_CS, 0.7, nx, ny, kappa=0.0, tau=1.0, k=1.0, cfd_alpha=al, bc_y=1)
+    y = np.arange(ny)
+    for m in [1, 3, ny // 2, ny - 1]:
+        th = np.pi * m / ny
+        kp = (a * np.sin(th) + b / 2 * np.sin(2 * th)) / (1 + 2 * al * np.cos(th))
+        ph = np.pi * ((m * (2 * y + 1)) % (4 * ny)) / (2 * ny)   # theta (y + 1/2), reduced
+        u = np.repeat(np.cos(ph)[:, None], nx, axis=1)
+        d1 = oracle.cfm_columns(p, u)
+        d2 = oracle.cfm_columns(p, u, second=True)
+        np.testing.assert_allclose(d1[:, 0], -kp * np.sin(ph), rtol=0, atol=4e-14)
+        np.testing.assert_allclose(d2[:, 1], -kp * kp * np.cos(ph), rtol=0, atol=4e-14)
+    # and the extension's dense system (2 ny periodic line) on a random column
+    u = np.random.default_rng(ny).standard_normal((ny, nx))
+    L, Rm = _dense(2 * ny, al, a, b)
+    for x in range(nx):
+        ext = np.concatenate([u[:, x], u[::-1, x]])
+        ref = np.linalg.solve(L, Rm @ ext)[:ny]
+        np.testing.assert_allclose(oracle.cfm_columns(p, u)[:, x], ref, rtol=0, atol=1e-13)
