@@ -86,7 +86,31 @@ typedef struct {
                            +INFINITY switches it off */
     double cfd_alpha;   /* compact scheme: 1/3 (sixth order, Eq. 39) or 1/4 (Eq. 38) */
     double wall_ux;     /* x-velocity of both walls (bc_y = 1); 0 for resting walls */
+    int32_t collision;  /* lbm_collision: BGK (Eq. 1) or MRT (Eq. 4) */
+    int32_t force;      /* lbm_force: chemical potential (Eq. 12) or pseudopotential */
+    double s_e, s_eps, s_q;  /* MRT rates of the energy, energy-square and energy-flux
+                                moments, each in (0, 2) (Eq. 4; the paper uses 1.64,
+                                1.54, 1.9); the stress moments relax at 1/tau.
+                                Ignored by BGK. */
 } lbm_params;
+
+/* Collision operator (Sec. 2). */
+typedef enum {
+    LBM_COLLISION_BGK = 0,  /* single relaxation time tau, Eq. 1 */
+    LBM_COLLISION_MRT = 1   /* multiple relaxation times, Eq. 4: moments (rho, e, eps,
+                               j_x, q_x, j_y, q_y, p_xx, p_xy) relaxed by
+                               S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 1/tau, 1/tau) */
+} lbm_collision;
+
+/* Nonideal force. */
+typedef enum {
+    LBM_FORCE_CP = 0,  /* chemical potential, F = -rho grad mu + c_s^2 grad rho (Eq. 12) */
+    LBM_FORCE_SC = 1   /* pseudopotential comparison model of Sec. 5.1 with k and the
+                          compact scheme: F = -G c_s^2 psi grad psi, G = -1, effective
+                          mass psi = sqrt(2 (rho c_s^2 - k^2 p0(rho)) / c_s^2) from the EOS
+                          (Eq. 29; 0 where the root's argument is negative).  kappa and
+                          mu_cap do not apply; lbm_force_fields returns psi as mu. */
+} lbm_force;
 
 /* ---- host-only thermodynamics (no device needed) ----------------------- */
 
@@ -113,6 +137,7 @@ size_t lbm_workspace_bytes(const lbm_params *p);
  *   device_ws:      NULL (the library allocates) or a caller-owned device
  *                   buffer of lbm_workspace_bytes(p) bytes, 256-byte aligned,
  *                   that must outlive the context.
+ * With LBM_FORCE_SC the initial density must lie inside the EOS domain.
  * Fails with LBM_E_INVALID for unsupported parameters, LBM_E_DOMAIN when a
  * density is not positive and finite, or (with the limit switched off)
  * outside the EOS domain (rho >= 1/b, or b rho / 4 >= 1 for CS).  *out is
@@ -248,7 +273,7 @@ typedef struct lbm_batch lbm_batch;
 /* Create a batch of nsims simulations.  params[s], rho0[s], ux0[s], uy0[s]
  * as for lbm_init (host arrays; ux0/uy0 may be NULL, or hold NULL entries,
  * for rest).  Each simulation needs 64 <= nx, ny <= 1024 with nx and ny
- * multiples of 8.  Fails as lbm_init would, naming the simulation in
+ * multiples of 8, and all use the same collision operator.  Fails as lbm_init would, naming the simulation in
  * lbm_batch_last_error(NULL). */
 lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const double *const *rho0,
                             const double *const *ux0, const double *const *uy0, lbm_batch **out);

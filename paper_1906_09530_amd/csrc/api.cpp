@@ -105,6 +105,14 @@ lbm_status validate(const lbm_params *p, std::string *why)
     if (!finite(p->wall_ux)) return bad("wall_ux must be finite");
     if (std::fabs(p->cfd_alpha - 1.0 / 3.0) > 1e-15 && std::fabs(p->cfd_alpha - 0.25) > 1e-15)
         return bad("cfd_alpha must be 1/3 or 1/4");
+    if (p->collision != LBM_COLLISION_BGK && p->collision != LBM_COLLISION_MRT)
+        return bad("collision must be LBM_COLLISION_BGK or LBM_COLLISION_MRT");
+    if (p->force != LBM_FORCE_CP && p->force != LBM_FORCE_SC)
+        return bad("force must be LBM_FORCE_CP or LBM_FORCE_SC");
+    if (p->collision == LBM_COLLISION_MRT) {
+        for (double r : {p->s_e, p->s_eps, p->s_q})
+            if (!(finite(r) && r > 0 && r < 2)) return bad("MRT rates must lie in (0, 2)");
+    }
     return LBM_OK;
 }
 
@@ -145,6 +153,13 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     k.inv_tau = 1.0 / p->tau;
     k.mu_cap = p->mu_cap;
     k.wall_ux = p->wall_ux;
+    k.sc = p->force == LBM_FORCE_SC;
+    k.mrt = p->collision == LBM_COLLISION_MRT;
+    // MRT: s_k / |M_k|^2 of (e, eps, q_x, q_y, p_xx, p_xy), |M_k|^2 = 36, 36,
+    // 12, 12, 4, 4 for the orthogonal moment basis of Eq. 4
+    const double rates[6] = {p->s_e, p->s_eps, p->s_q, p->s_q, 1.0 / p->tau, 1.0 / p->tau};
+    const double norms[6] = {36.0, 36.0, 12.0, 12.0, 4.0, 4.0};
+    for (int i = 0; i < 6; ++i) k.mrt_w[i] = k.mrt ? rates[i] / norms[i] : 0.0;
     const long double al = std::fabs(p->cfd_alpha - 0.25) < 1e-15 ? 0.25L : 1.0L / 3.0L;
     k.cfd_a2 = (double)(2.0L * (al + 2.0L) / 3.0L / 2.0L);  // a/2, Eq. 38
     k.cfd_b4 = (double)((4.0L * al - 1.0L) / 3.0L / 4.0L);  // b/4, Eq. 38
@@ -183,7 +198,8 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
 lbm_status check_density(const lbm_params *p, const double *rho, const double *ux,
                          const double *uy, size_t N, std::string *why)
 {
-    const bool cap_off = std::isinf(p->mu_cap) && p->mu_cap > 0;
+    // the pseudopotential model has no upper limit of mu to fall back on
+    const bool cap_off = (std::isinf(p->mu_cap) && p->mu_cap > 0) || p->force == LBM_FORCE_SC;
     for (size_t n = 0; n < N; ++n) {
         const double r = rho[n];
         if (!(finite(r) && r > 0)) {
@@ -889,7 +905,7 @@ hipError_t batch_enqueue(lbm_batch *b, int64_t nsteps)
                                      b->col_lc, b->col_wmax, b->stream);
         if (e == hipSuccess)
             e = launch_batch_rows_collide(b->d_kp, b->d_sb, b->d_rows, b->n_rows, b->parity,
-                                          b->row_lds, b->stream);
+                                          b->row_lds, b->kp[0].mrt != 0, b->stream);
         b->parity ^= 1;
     }
     return e;
@@ -965,6 +981,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
             return give_up(LBM_E_INVALID, who + "batch meshes need 64 <= nx, ny <= 1024, multiples of 8");
         if (!make_kparams(p, &b->kp[s], &why)) return give_up(LBM_E_INVALID, who + why);
         if (!b->kp[s].use_iir_rows) return give_up(LBM_E_INVALID, who + "row pass shape");
+        if (p->collision != params[0].collision)
+            return give_up(LBM_E_INVALID, who + "every simulation of a batch needs the same collision");
         if (!rho0[s]) return give_up(LBM_E_INVALID, who + "rho0 is NULL");
         st = check_density(p, rho0[s], ux0 ? ux0[s] : nullptr, uy0 ? uy0[s] : nullptr,
                            (size_t)p->nx * p->ny, &why);

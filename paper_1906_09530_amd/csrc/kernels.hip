@@ -169,9 +169,12 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
         rr[k] = r;
         bA[E.e[k]] = r;
         rho_out[node] = r;
-        if (p.kappa_zero) mux_out[node] = p.k2 * mu0_capped(p, r);
+        if (p.sc)  // pseudopotential model: the plane holds psi
+            mux_out[node] = sc_psi(p, r);
+        else if (p.kappa_zero)
+            mux_out[node] = p.k2 * mu0_capped(p, r);
     }
-    if (p.kappa_zero) return;  // uniform: the Laplacian is not used
+    if (p.kappa_zero || p.sc) return;  // uniform: the Laplacian is not used
     __syncthreads();
     double d1[kElemsPerThread], d2[kElemsPerThread];
     double *res = cfm_solve(p, m, E, bA, bB, 1.0, d1);
@@ -210,6 +213,27 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu(KParams p,
     double *bA = smem, *bB = smem + p.cols_per_block * ny;
     const LineMap<FAST> m{ny, cols, true, p.bc_y != 0};
     const Elems E = make_elems(m);
+    if (p.sc) {
+        // pseudopotential model: F_y = -G c_s^2 psi d/dy psi with G = -1;
+        // psi goes on to the collision pass in the mu plane
+        double ps[kElemsPerThread], dps[kElemsPerThread];
+#pragma unroll
+        for (int k = 0; k < kElemsPerThread; ++k) {
+            if (!E.ok[k]) continue;
+            const size_t node = (size_t)E.j[k] * nx + x0 + E.l[k];
+            ps[k] = mux[node];
+            mu_out[node] = ps[k];
+            bA[E.e[k]] = ps[k];
+        }
+        __syncthreads();
+        cfm_solve(p, m, E, bA, bB, 1.0, dps);
+#pragma unroll
+        for (int k = 0; k < kElemsPerThread; ++k) {
+            if (!E.ok[k]) continue;
+            fy_out[(size_t)E.j[k] * nx + x0 + E.l[k]] = CS2 * ps[k] * dps[k];
+        }
+        return;
+    }
     double r[kElemsPerThread];
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
@@ -268,12 +292,15 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
         bA[E.e[k]] = rho[k];
     }
     __syncthreads();
-    double dxr[kElemsPerThread], dxm[kElemsPerThread];
-    cfm_solve(p, m, E, bA, bB, 1.0, dxr);
+    double dxr[kElemsPerThread], dxm[kElemsPerThread], mv[kElemsPerThread];
+    if (!p.sc) {
+        cfm_solve(p, m, E, bA, bB, 1.0, dxr);
+    }
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
-        bA[E.e[k]] = mu[(size_t)(y0 + E.l[k]) * nx + E.j[k]];
+        mv[k] = mu[(size_t)(y0 + E.l[k]) * nx + E.j[k]];
+        bA[E.e[k]] = mv[k];
     }
     __syncthreads();
     cfm_solve(p, m, E, bA, bB, 1.0, dxm);
@@ -288,7 +315,8 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
         const double rh = rho[k];
         const double jx = (q[1] - q[3]) + (q[5] - q[6]) + (q[8] - q[7]);
         const double jy = (q[2] - q[4]) + (q[5] - q[8]) + (q[6] - q[7]);
-        const double Fx = -rh * dxm[k] + CS2 * dxr[k];
+        // Eq. 12, or the pseudopotential force (mv holds psi)
+        const double Fx = p.sc ? CS2 * mv[k] * dxm[k] : -rh * dxm[k] + CS2 * dxr[k];
         const double Fy = fy[node];
         const double ux = jx / rh, uy = jy / rh;
         if (OBSERVE) {
@@ -300,11 +328,15 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
         }
         const double vx2 = ux + Fx / rh, vy2 = uy + Fy / rh;
         const double uu = ux * ux + uy * uy, uu2 = vx2 * vx2 + vy2 * vy2;
+        double dm[6];
+        if (p.mrt) mrt_departures(p, q, rh, jx, jy, ux, uy, dm);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const double eq = feq(i, rh, ux, uy, uu);
             const double eq2 = feq(i, rh, vx2, vy2, uu2);
-            const double fs = q[i] - (q[i] - eq) * p.inv_tau + (eq2 - eq);
+            // BGK (Eq. 1) or MRT (Eq. 4), with the exact-difference force (Eq. 5)
+            const double fs = p.mrt ? mrt_relax(i, q[i], dm) + (eq2 - eq)
+                                    : q[i] - (q[i] - eq) * p.inv_tau + (eq2 - eq);
             int tx = x + EX[i];
             tx = tx < 0 ? tx + nx : (tx >= nx ? tx - nx : tx);
             int ty = y + EY[i];

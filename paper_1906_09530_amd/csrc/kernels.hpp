@@ -27,6 +27,11 @@ struct KParams {
     double a, b, RT, A;  // EOS constants; A = a alpha(T)
     double eos_c1;       // A / b (RK, RKS) or A / (2 sqrt(2) b) (PR)
     double k2, kappa, inv_tau, mu_cap, wall_ux;
+    // collision: 0 BGK (Eq. 1), 1 MRT (Eq. 4) with mrt_w = s_k / |M_k|^2 of
+    // (e, eps, q_x, q_y, p_xx, p_xy); force: 0 chemical potential (Eq. 12),
+    // 1 pseudopotential comparison model (Sec. 5.1)
+    int mrt, sc;
+    double mrt_w[6];
     double cfd_a2, cfd_b4;  // a/2 and b/4 of Eq. 37 (h = 1)
     double pcr_c[kMaxStages], pcr_g[kMaxStages];
     // factorised inverse of the circulant compact-scheme matrix (fast path):
@@ -116,9 +121,10 @@ hipError_t launch_batch_rows_rho(const KParams *kps, const SimBuffers *sb, const
                                  int nwork, int parity, size_t lds, hipStream_t s);
 hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const WorkItem *work,
                                 int nwork, int col_elems, int lc, int wmax, hipStream_t s);
+// (mrt: every simulation of the batch uses the MRT collision of Eq. 4)
 hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
                                      const WorkItem *work, int nwork, int parity, size_t lds,
-                                     hipStream_t s);
+                                     bool mrt, hipStream_t s);
 
 // Fast-path kernels (kernels_iir.hip) and their eligibility.
 bool iir_rows_ok(const KParams &p);

@@ -260,9 +260,12 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     double mx[LC];
     if (m.ok) {
 #pragma unroll
-        for (int k = 0; k < LC; ++k) mx[k] = p.k2 * mu0_capped(p, rho[k]);
+        for (int k = 0; k < LC; ++k)
+            mx[k] = p.sc ? sc_psi(p, rho[k]) : p.k2 * mu0_capped(p, rho[k]);
     }
-    if (p.kappa_zero) {  // uniform: the Laplacian is not used
+    // uniform: the Laplacian is not used (kappa = 0), or the pseudopotential
+    // model, whose plane holds psi
+    if (p.kappa_zero || p.sc) {
         if (m.ok) vstore<LC>(mux_out + base, mx);
         return;
     }
@@ -317,6 +320,26 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
     const LineLds L = carve_lds(smem, m);
     const size_t col = x0 + m.l;
     const int j0 = m.c * LC;
+    if (p.sc) {
+        // pseudopotential model: F_y = -G c_s^2 psi d/dy psi with G = -1; psi
+        // is passed on to the collision pass in the mu plane
+        double ps[LC], dps[LC];
+        if (m.ok) {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                const size_t node = (size_t)(j0 + k) * nx + col;
+                ps[k] = mux[node];
+                mu_out[node] = ps[k];
+            }
+        }
+        iir_solve<LC>(p, m, p.iir_qL_col, ps, 1.0, L, dps);
+        if (m.ok) {
+#pragma unroll
+            for (int k = 0; k < LC; ++k)
+                fy_out[(size_t)(j0 + k) * nx + col] = CS2 * ps[k] * dps[k];
+        }
+        return;
+    }
     double r[LC];
     if (m.ok) {
 #pragma unroll
@@ -371,7 +394,7 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
 // derivative pass k_rows_fx_iir), so it has no line solve; the density groups
 // of the segment's first and last node, which receive populations from the
 // neighbouring segments, are left to k_group_seams.
-template <bool OBSERVE, bool KEEP, bool SEG = false>
+template <bool OBSERVE, bool KEEP, bool SEG = false, bool MRT = false>
 __device__ __forceinline__ void rows_collide_body(
     const KParams &p, int y0, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
@@ -428,13 +451,15 @@ __device__ __forceinline__ void rows_collide_body(
             vload<LC>(fx_in + base, Fx);
         }
     } else {
+        // F_x of Eq. 12, or of the pseudopotential model (mv holds psi)
         double dxr[LC], dxm[LC];
-        iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, dxr);
+        if (!p.sc) iir_solve<LC>(p, m, p.iir_qL_row, rho, 1.0, L, dxr);
         iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
         if (m.ok) {
             vload<LC>(fy + base, Fy);
 #pragma unroll
-            for (int k = 0; k < LC; ++k) Fx[k] = -rho[k] * dxm[k] + CS2 * dxr[k];
+            for (int k = 0; k < LC; ++k)
+                Fx[k] = p.sc ? CS2 * mv[k] * dxm[k] : -rho[k] * dxm[k] + CS2 * dxr[k];
         }
     }
     if (OBSERVE) {
@@ -472,6 +497,28 @@ __device__ __forceinline__ void rows_collide_body(
             uu[k] = ux[k] * ux[k] + uy[k] * uy[k];
             uu2[k] = vx2[k] * vx2[k] + vy2[k] * vy2[k];
         }
+        // MRT (Eq. 4): the relaxed moments' departures from equilibrium need
+        // all nine populations of a node before the first is collided
+        double dm[MRT ? LC : 1][6];
+        if (MRT) {
+            double qa[9][LC];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if (KEEP) {
+#pragma unroll
+                    for (int k = 0; k < LC; ++k) qa[i][k] = fi[KEEP ? i : 0][k];
+                } else {
+                    vload<LC>(f + i * N + base, qa[i]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                double qk[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) qk[i] = qa[i][k];
+                mrt_departures(p, qk, rho[k], jx[k], jy[k], ux[k], uy[k], dm[MRT ? k : 0]);
+            }
+        }
         // collision and push streaming, one population at a time: population
         // i of node (x, y) goes to (x + e_x, y + e_y)
 #pragma unroll
@@ -487,7 +534,10 @@ __device__ __forceinline__ void rows_collide_body(
             for (int k = 0; k < LC; ++k) {
                 const double eq = feq(i, rho[k], ux[k], uy[k], uu[k]);
                 const double eq2 = feq(i, rho[k], vx2[k], vy2[k], uu2[k]);
-                v[k] = q[k] - (q[k] - eq) * p.inv_tau + (eq2 - eq);
+                if (MRT)
+                    v[k] = mrt_relax(i, q[k], dm[MRT ? k : 0]) + (eq2 - eq);
+                else
+                    v[k] = q[k] - (q[k] - eq) * p.inv_tau + (eq2 - eq);
             }
             const bool refl = (EY[i] < 0 && refl_d) || (EY[i] > 0 && refl_u);
             if (refl) {
@@ -660,15 +710,15 @@ __device__ __forceinline__ void rows_collide_body(
     vstore<LC>(gout + dn, gd);
 }
 
-template <int MAXT, bool OBSERVE, bool KEEP>
+template <int MAXT, bool OBSERVE, bool KEEP, bool MRT = false>
 __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
     KParams p, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
     double *__restrict__ o_rho, double *__restrict__ o_vx, double *__restrict__ o_vy,
     double *__restrict__ o_fx)
 {
-    rows_collide_body<OBSERVE, KEEP>(p, blockIdx.x * p.rows_per_block, f, mu, fy, fout, gout,
-                                     o_rho, o_vx, o_vy, o_fx);
+    rows_collide_body<OBSERVE, KEEP, false, MRT>(p, blockIdx.x * p.rows_per_block, f, mu, fy,
+                                                 fout, gout, o_rho, o_vx, o_vy, o_fx);
 }
 
 // ---- split collision pass for long rows -------------------------------
@@ -679,7 +729,8 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
 // threads that hold f in registers (k_collide_seg_iir); k_group_seams then
 // forms the density groups of the segments' end nodes from the finished f.
 
-// F_x = -rho d/dx mu + c_s^2 d/dx rho (Eq. 12) from the rho and mu planes.
+// F_x = -rho d/dx mu + c_s^2 d/dx rho (Eq. 12) from the rho and mu planes
+// (pseudopotential model: c_s^2 psi d/dx psi, psi in the mu plane).
 __device__ __forceinline__ void rows_fx_body(const KParams &p, int y0,
                                              const double *__restrict__ rho,
                                              const double *__restrict__ mu,
@@ -697,12 +748,13 @@ __device__ __forceinline__ void rows_fx_body(const KParams &p, int y0,
         vload<LC>(mu + base, mv);
     }
     double dxr[LC], dxm[LC];
-    iir_solve<LC>(p, m, p.iir_qL_row, r, 1.0, L, dxr);
+    if (!p.sc) iir_solve<LC>(p, m, p.iir_qL_row, r, 1.0, L, dxr);
     iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
     if (m.ok) {
         double Fx[LC];
 #pragma unroll
-        for (int k = 0; k < LC; ++k) Fx[k] = -r[k] * dxm[k] + CS2 * dxr[k];
+        for (int k = 0; k < LC; ++k)
+            Fx[k] = p.sc ? CS2 * mv[k] * dxm[k] : -r[k] * dxm[k] + CS2 * dxr[k];
         vstore<LC>(fx_out + base, Fx);
     }
 }
@@ -715,15 +767,15 @@ __global__ __launch_bounds__(MAXT) void k_rows_fx_iir(KParams p, const double *_
     rows_fx_body(p, blockIdx.x * p.rows_per_block, rho, mu, fx_out);
 }
 
-template <bool KEEP>
+template <bool KEEP, bool MRT>
 __global__ __launch_bounds__(256) void k_collide_seg_iir(
     KParams p, const double *__restrict__ f, const double *__restrict__ fy,
     const double *__restrict__ fx, double *__restrict__ fout, double *__restrict__ gout)
 {
     const int nseg = p.nx / p.seg_len;
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
-    rows_collide_body<false, KEEP, true>(p, y, f, nullptr, fy, fout, gout, nullptr, nullptr,
-                                         nullptr, nullptr, sg * p.seg_len, fx);
+    rows_collide_body<false, KEEP, true, MRT>(p, y, f, nullptr, fy, fout, gout, nullptr,
+                                              nullptr, nullptr, nullptr, sg * p.seg_len, fx);
 }
 
 // Density groups (as k_density_groups) at the first and last node of every
@@ -769,6 +821,7 @@ __global__ __launch_bounds__(MAXT) void kb_cols_mu(const KParams *__restrict__ k
     cols_mu_body<LC>(kps[w.sim], w.start, b.rho, b.mux, b.mu, b.fy);
 }
 
+template <bool MRT>
 __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict__ kps,
                                                        const SimBuffers *__restrict__ sb,
                                                        const WorkItem *__restrict__ work,
@@ -776,9 +829,9 @@ __global__ __launch_bounds__(256) void kb_rows_collide(const KParams *__restrict
 {
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
-    rows_collide_body<false, true>(kps[w.sim], w.start, b.f[parity], b.mu, b.fy,
-                                   b.f[1 - parity], b.g[1 - parity], nullptr, nullptr, nullptr,
-                                   nullptr);
+    rows_collide_body<false, true, false, MRT>(kps[w.sim], w.start, b.f[parity], b.mu, b.fy,
+                                               b.f[1 - parity], b.g[1 - parity], nullptr,
+                                               nullptr, nullptr, nullptr);
 }
 
 }  // namespace
@@ -829,10 +882,15 @@ hipError_t launch_batch_cols_mu(const KParams *kps, const SimBuffers *sb, const 
 
 hipError_t launch_batch_rows_collide(const KParams *kps, const SimBuffers *sb,
                                      const WorkItem *work, int nwork, int parity, size_t lds,
-                                     hipStream_t s)
+                                     bool mrt, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_rows_collide, dim3(nwork), dim3(256), lds, s, kps, sb, work, parity);
+    if (mrt)
+        hipLaunchKernelGGL(kb_rows_collide<true>, dim3(nwork), dim3(256), lds, s, kps, sb, work,
+                           parity);
+    else
+        hipLaunchKernelGGL(kb_rows_collide<false>, dim3(nwork), dim3(256), lds, s, kps, sb, work,
+                           parity);
     return hipGetLastError();
 }
 
@@ -914,12 +972,16 @@ hipError_t launch_collide_split_iir(const KParams &p, const double *f, const dou
     if (e != hipSuccess) return e;
     const int S = p.seg_len, blocks = p.ny * (p.nx / S);
     const size_t lds = line_lds(S, 1, kRowLC, true);
-    if (p.row_keep)
-        hipLaunchKernelGGL(k_collide_seg_iir<true>, dim3(blocks), dim3(S / kRowLC), lds, s,
-                           p, f, fy, fx, fout, gout);
+#define ARGS dim3(blocks), dim3(S / kRowLC), lds, s, p, f, fy, fx, fout, gout
+    if (p.row_keep && p.mrt)
+        hipLaunchKernelGGL((k_collide_seg_iir<true, true>), ARGS);
+    else if (p.row_keep)
+        hipLaunchKernelGGL((k_collide_seg_iir<true, false>), ARGS);
+    else if (p.mrt)
+        hipLaunchKernelGGL((k_collide_seg_iir<false, true>), ARGS);
     else
-        hipLaunchKernelGGL(k_collide_seg_iir<false>, dim3(blocks), dim3(S / kRowLC), lds, s,
-                           p, f, fy, fx, fout, gout);
+        hipLaunchKernelGGL((k_collide_seg_iir<false, false>), ARGS);
+#undef ARGS
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t seams = (size_t)p.ny * (p.nx / S) * 2;
     hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
@@ -941,8 +1003,13 @@ hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const doub
     if (observe)
         CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, true, false>),
                           (k_rows_collide_iir<1024, true, false>), ARGS);
+    else if (keep && p.mrt)
+        hipLaunchKernelGGL((k_rows_collide_iir<256, false, true, true>), ARGS);
     else if (keep)
         hipLaunchKernelGGL((k_rows_collide_iir<256, false, true>), ARGS);
+    else if (p.mrt)
+        CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, false, false, true>),
+                          (k_rows_collide_iir<1024, false, false, true>), ARGS);
     else
         CPLBM_IIR_THREADS(T, (k_rows_collide_iir<256, false, false>),
                           (k_rows_collide_iir<1024, false, false>), ARGS);
