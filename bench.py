@@ -7,17 +7,21 @@ tanh initial interface of width 10 between the Maxwell densities
 (Sec. 5.6), k = 0.1, kappa = 0.004, sixth-order compact scheme.
 
 One "step" is one lattice-Boltzmann time step of the whole mesh (the three
-kernels of the solver).  Prints one JSON line with MLUPS (whole job), the
-roofline entry of the dominant kernel (algorithmic bytes / its average
-duration, HIP events on the solver's stream) and the CPU oracle timed on a
-bounded sample of the same workload.  The "sweep" entry times a batched
+kernels of the solver).  Prints one JSON line with MLUPS (whole job) of this
+workload, its kernels timed inside the step sequence (HIP events around every
+launch), a report of the drop after the run (largest speed, bulk densities
+against the Maxwell pair, pressure jump times radius), the roofline entry of
+the dominant kernel on the 4096 x 2048 splash between walls (a working set of
+~1.4 GB, far beyond the 256 MB last-level cache, so the bytes come from HBM),
+and the CPU oracle timed on a bounded sample of the drop, on one core and on
+all cores.  The "sweep" entry times a batched
 sweep of simulations of uneven size to convergence against running each on
 its own (the plain method); the "warm_start" entry trains the warm-start
 network on solver-converged drops and compares steps and time to converge
 from its proposal and from the tanh start.
 
     python bench.py [--gpus 1] [--steps 20000] [--warmup 200] [--sweep small|full|none]
-                    [--warmstart small|full|cs-small|cs-full|none]
+                    [--warmstart small|full|cs-small|cs-full|none] [--splash hbm|full|none]
 """
 import argparse
 import json
@@ -31,21 +35,29 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (D2Q9 FP64) + % peak HBM BW; sweep/warm-start time-to-converge vs plain"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per node of each kernel (FP64):
+# Bytes per node of each kernel (FP64) as this design moves them:
 #   row pass A: read the three density groups of the state (3 x 8), write rho
 #     and the row part of mu (2 x 8)
 #   column pass B: read rho and the row part of mu; write mu, F_y
 #   row pass C: read f (9 x 8), mu, F_y; write f (9 x 8) and its three
 #     density groups (3 x 8)
+# and, for the roofline, the algorithmic count of the collide-and-stream
+# kernel: read f and the two force or chemical-potential inputs, write f
+# (72 + 24 + 72 = 168 B per lattice update); the floor of any scheme is f
+# read and written once (144 B per update).
 PASS_NAMES = ["rows_rho", "cols_mu", "rows_collide"]
 PASS_BYTES = [40, 32, 184]
+SPLIT_NAMES = ["rows_rho", "cols_mu", "rows_fx", "collide_seg", "group_seams"]
+SPLIT_BYTES = [40, 32, 24, 184, 0]
+COLLIDE_ALG_BYTES = 168
+FLOOR_BYTES = 144
 
 NX = NY = 1024
 CFG = dict(T_r=0.5, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0, radius=200.0, width=10.0)
 
 
 KERNEL_SOURCES = ["kernels.hip", "kernels_iir.hip", "kernels.hpp", "physics.hpp", "lnx.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_pr1024.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_splash4096x2048.json")
 
 
 def kernel_sources_sha256():
@@ -326,15 +338,63 @@ def splash_bench(torch, lbm, inputs):
     return out
 
 
+def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
+    """The 4096 x 2048 splash between walls at rest (Sec. 5.5), autotuned: a
+    whole-step rate over `steps` steps (events on the solver's stream) and each
+    kernel timed inside the step sequence over `kernel_steps` steps.  Its
+    working set (two f buffers, two density-group buffers and the planes,
+    ~1.4 GB) is far beyond the last-level cache, so it is the HBM point."""
+    import numpy as np
+    c = SPLASH
+    nx, ny = c["nx"], c["ny"]
+    p = lbm.params(lbm.EOS_CS, c["T_r"], nx, ny, kappa=c["kappa"], tau=c["tau"], k=c["k"],
+                   mu_cap=c["mu_cap"], bc_y=1)
+    g, l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, c["radius"], c["width"], film=c["film"],
+                                   drop_uy=c["drop_uy"])
+    stream = torch.cuda.current_stream()
+    d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+    s = lbm.Solver(p, *d, stream=stream.cuda_stream)
+    s.step(20)
+    s.autotune(5)
+    s.step(20)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / steps
+    ms = s.time_step_kernels(kernel_steps)
+    r = s.moments()[0]
+    finite = bool(np.isfinite(r).all())
+    s.close()
+    names = SPLIT_NAMES if len(ms) == 5 else PASS_NAMES
+    nbytes = SPLIT_BYTES if len(ms) == 5 else PASS_BYTES
+    N = nx * ny
+    dom = int(np.argmax(ms))
+    return {"workload": "drop splashing on a 40-node film between walls, CS, 4096x2048, "
+                        "T/Tc=0.6, R=100, tau=0.6, k=0.2, kappa=0.1",
+            "nx": nx, "ny": ny, "finite": finite, "steps": steps,
+            "ms_per_step": round(ms_step, 6), "MLUPS": round(N / (ms_step * 1e-3) / 1e6, 1),
+            "floor_equivalent_GB_s": round(FLOOR_BYTES * N / (ms_step * 1e-3) / 1e9, 1),
+            "kernels": {names[i]: {"avg_ms": round(ms[i], 6),
+                                   "design_bytes_per_node": nbytes[i],
+                                   "design_GB_s": round(nbytes[i] * N / (ms[i] * 1e-3) / 1e9, 1)}
+                        for i in range(len(ms))},
+            "dominant": names[dom], "dominant_ms": ms[dom]}
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
 
 
-def cpu_baseline(budget_s=15.0):
-    """The oracle on the host, single thread, on the first steps of the same
-    workload until about `budget_s` of CPU work.  Its inputs are built from
-    the oracle's own coexistence densities."""
+def cpu_baseline(budget_s=12.0, all_cores=True):
+    """The oracle on the host on the first steps of the same workload until
+    about `budget_s` of work: single-threaded, then (all_cores) its OpenMP
+    build (bitwise the same results) on every core this process may use.
+    Its inputs are built from the oracle's own coexistence densities."""
     import oracle
     from oracle import analytic as A
     from paper_1906_09530_amd import inputs
@@ -342,18 +402,39 @@ def cpu_baseline(budget_s=15.0):
                   mu_cap=CFG["mu_cap"])
     g, l = (float(v) for v in A.EOS(A.EOS_PR).maxwell(CFG["T_r"]))
     rho0, ux0, uy0 = inputs.droplet(NX, NY, g, l, CFG["radius"], CFG["width"])
-    f = oracle.init(op, rho0, ux0, uy0)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.step(op, f)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": NX * NY * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "first %d steps of the same 1024x1024 PR drop, single-threaded C oracle "
-                      "(%.1f s)" % (steps, el)}
+
+    def timed(threads):
+        used = oracle.threads(threads)
+        f = oracle.init(op, rho0, ux0, uy0)
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.step(op, f)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+        return NX * NY * steps / el / 1e6, steps, el, used
+
+    try:
+        one, s1, e1, _ = timed(1)
+        if not all_cores:
+            return {"value": one, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+                    "sample": "first %d steps of the same 1024x1024 PR drop, single-threaded C "
+                              "oracle (%.1f s)" % (s1, e1)}
+        # every core this process may use, within the thread count the
+        # environment allows (OMP_NUM_THREADS)
+        cores = len(os.sched_getaffinity(0))
+        env = os.environ.get("OMP_NUM_THREADS", "")
+        if env.isdigit() and int(env) > 0:
+            cores = min(cores, int(env))
+        many, s2, e2, used = timed(cores)
+    finally:
+        oracle.threads(1)
+    return {"value": many, "unit": "MLUPS", "cores": used, "kind": "oracle",
+            "single_core_value": one,
+            "sample": "first %d steps of the same 1024x1024 PR drop, C oracle on %d threads "
+                      "(OpenMP over lines and nodes, %.1f s); single-threaded: %d steps in %.1f s"
+                      % (s2, used, e2, s1, e1)}
 
 
 def main():
@@ -372,9 +453,12 @@ def main():
     ap.add_argument("--sweep", choices=["small", "full", "none"], default="small",
                     help="batched sweep vs one run per member (time to converge): 16 members "
                          "up to 256^2 (small), 64 members up to 512^2 (full, minutes), or none")
-    ap.add_argument("--splash", choices=["full", "none"], default="none",
-                    help="also run the 4096 x 2048 splash between walls in two frames "
-                         "(10,000 steps each, about 20 s)")
+    ap.add_argument("--splash", choices=["hbm", "full", "none"], default="hbm",
+                    help="the 4096 x 2048 splash between walls: its whole-step rate and "
+                         "in-sequence kernel times, the roofline point (hbm, default); also "
+                         "the 10,000-step run in two frames (full, about 20 s more); or none")
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="steps over which each kernel is timed inside the sequence")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (a kernel of known "
                          "traffic, to calibrate FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -439,27 +523,45 @@ def main():
     ms_per_step = ms / args.steps
     mlups = NX * NY / (ms_per_step * 1e-3) / 1e6
 
-    # per-kernel durations with HIP events on the solver's stream
-    print("per-kernel timing over %d steps" % args.pass_steps, file=sys.stderr, flush=True)
-    pass_ms = s.time_passes(args.pass_steps)
-    gbs = [PASS_BYTES[i] * NX * NY / (pass_ms[i] * 1e-3) / 1e9 for i in range(3)]
-    dom = int(np.argmax(pass_ms))
-
-    copy_gbs = copy_bandwidth(torch, PASS_BYTES[dom] * NX * NY)
-    copy_big_gbs = copy_bandwidth(torch, 2 << 30, reps=5)
-    r, vx, vy = s.moments()
-    finite = bool(np.isfinite(r).all())
-    inside = r[NY // 2, NX // 2]
-    outside = r[0, 0]
-    steps_total = s.steps_taken
+    # the drop after warmup + timed steps, before the kernel timing steps
+    report = drop_report(lbm, s, p, rho_g, rho_l)
+    print("per-kernel timing inside the step sequence over %d steps" % args.kernel_steps,
+          file=sys.stderr, flush=True)
+    kms = s.time_step_kernels(args.kernel_steps)
     s.close()
+    N = NX * NY
 
-    traffic = measured_traffic(PASS_NAMES[dom])
-    step_traffic = [measured_traffic(n) for n in PASS_NAMES]
+    splash = None
+    if args.splash != "none":
+        print("4096 x 2048 splash: HBM point", file=sys.stderr, flush=True)
+        splash = splash_hbm(torch, lbm, inputs, kernel_steps=args.kernel_steps)
+        if args.splash == "full":
+            splash["two_frames_10000_steps"] = splash_bench(torch, lbm, inputs)
+    copy_big_gbs = copy_bandwidth(torch, 2 << 30, reps=5)
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
     warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)
-    splash = None if args.splash == "none" else splash_bench(torch, lbm, inputs)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
+
+    roofline = None
+    if splash is not None:
+        nodes = splash["nx"] * splash["ny"]
+        dms = splash["dominant_ms"]
+        ach = COLLIDE_ALG_BYTES * nodes / (dms * 1e-3) / 1e9
+        roofline = {
+            "kernel": splash["dominant"],
+            "workload": "4096x2048 CS splash between walls (out of cache)",
+            "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(splash["dominant"]),
+            "traffic_unit": "bytes/launch",
+            "algorithmic_bytes_per_node": COLLIDE_ALG_BYTES,
+            "design_bytes_per_node": splash["kernels"][splash["dominant"]]["design_bytes_per_node"],
+            "avg_ms": round(dms, 6),
+            "timing": "HIP events around every launch inside the step sequence",
+            "step_floor_frac": round(splash["floor_equivalent_GB_s"] / HBM_PEAK_GBS, 4),
+            "device_copy_1GiB_GB_s": round(copy_big_gbs, 1),
+        }
+        del splash["dominant_ms"]
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -480,42 +582,47 @@ def main():
             "k": CFG["k"], "kappa": CFG["kappa"], "tau": CFG["tau"], "mu_cap": CFG["mu_cap"],
             "radius": CFG["radius"], "width": CFG["width"],
         },
-        "roofline": {
-            "kernel": PASS_NAMES[dom],
-            "bound": "hbm",
-            "achieved": round(gbs[dom], 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(gbs[dom] / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "traffic_unit": "bytes/launch",
-            "traffic_vs_algorithmic": (None if traffic is None else
-                                       round(traffic / (PASS_BYTES[dom] * NX * NY), 4)),
-            "bytes_per_node": PASS_BYTES[dom],
-            "avg_ms": round(pass_ms[dom], 6),
-            "device_copy_GB_s": round(copy_gbs, 1),
-            "device_copy_1GiB_GB_s": round(copy_big_gbs, 1),
-        },
-        "kernels": {PASS_NAMES[i]: {"avg_ms": round(pass_ms[i], 6), "GB_s": round(gbs[i], 1),
-                                    "bytes_per_node": PASS_BYTES[i]} for i in range(3)},
-        "step_algorithmic_GB_s": round(sum(PASS_BYTES) * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
+        "roofline": roofline,
+        # 1024^2 drop: its ~240 MB working set sits largely in the 256 MB
+        # last-level cache
+        "kernels": {PASS_NAMES[i]: {"avg_ms": round(kms[i], 6),
+                                    "design_bytes_per_node": PASS_BYTES[i],
+                                    "design_GB_s": round(PASS_BYTES[i] * N / (kms[i] * 1e-3) / 1e9,
+                                                         1)} for i in range(3)},
+        "kernels_note": "1024x1024 drop, timed inside the step sequence; cache-resident working set",
+        "collide_algorithmic_GB_s": round(COLLIDE_ALG_BYTES * N / (kms[2] * 1e-3) / 1e9, 1),
         # MLUPS x 144 B (f read and written once: the floor of any scheme)
-        "floor_equivalent_GB_s": round(144 * NX * NY / (ms_per_step * 1e-3) / 1e9, 1),
-        # HBM bytes of the three passes (FETCH_SIZE + WRITE_SIZE per launch,
-        # committed profile) over the step time
-        "step_measured_GB_s": (None if None in step_traffic else
-                               round(sum(step_traffic) / (ms_per_step * 1e-3) / 1e9, 1)),
+        "floor_equivalent_GB_s": round(FLOOR_BYTES * N / (ms_per_step * 1e-3) / 1e9, 1),
         "autotune_col_width_ms": {str(k): round(v, 6) for k, v in tune.items()},
         "wall_s": round(wall, 3),
-        "state": {"finite": finite, "steps": steps_total, "rho_center": float(inside),
-                  "rho_corner": float(outside), "max_speed": float(np.hypot(vx, vy).max()),
-                  "rho_g_maxwell": rho_g, "rho_l_maxwell": rho_l},
+        "drop_after_run": report,
+        "splash_hbm": splash,
         "sweep": sweep,
         "warm_start": warm,
-        "splash": splash,
         "cpu_baseline": cpu,
     }
     print(json.dumps(strict_json(out), allow_nan=False), flush=True)
+
+
+def drop_report(lbm, s, p, rho_g, rho_l):
+    """The static drop after the run: steps, largest speed |v| (the spurious
+    current once the drop has settled; Sec. 5.4), bulk densities inside and
+    outside against the Maxwell pair, the equimolar radius and the pressure
+    jump k^2 [p0(inside) - p0(outside)] times that radius (the surface
+    tension, were the drop at rest; Eq. 40)."""
+    import numpy as np
+    r, vx, vy = s.moments()
+    inside, outside = float(r[NY // 2, NX // 2]), float(r[0, 0])
+    radius = float(np.sqrt(((r - outside) / (inside - outside)).sum() / np.pi))
+    p_in = lbm.eos_values(p, inside)[0]
+    p_out = lbm.eos_values(p, outside)[0]
+    dp = p.k * p.k * (p_in - p_out)
+    return {"steps": s.steps_taken, "finite": bool(np.isfinite(r).all()),
+            "max_speed": float(np.hypot(vx, vy).max()),
+            "rho_inside": inside, "rho_outside": outside,
+            "rho_l_maxwell": rho_l, "rho_g_maxwell": rho_g,
+            "rel_inside_vs_maxwell": inside / rho_l - 1, "rel_outside_vs_maxwell": outside / rho_g - 1,
+            "equimolar_radius": radius, "pressure_jump": dp, "pressure_jump_x_radius": dp * radius}
 
 
 if __name__ == "__main__":

@@ -124,6 +124,11 @@ lbm_status lbm_critical_point(const lbm_params *p, double *T_c, double *rho_c, d
  * tanh fields of Eq. 41.  LBM_E_INVALID if T_r is not in (0, 1). */
 lbm_status lbm_maxwell(const lbm_params *p, double *rho_g, double *rho_l);
 
+/* Bulk pressure p0(rho) (Eqs. 14, 16, 18, 20) and chemical potential psi'(rho)
+ * (Eqs. 15, 17, 19, 21) at p->T_r, momentum units (either output may be
+ * NULL).  LBM_E_DOMAIN unless 0 < rho < 1/b (4/b for CS). */
+lbm_status lbm_eos_values(const lbm_params *p, double rho, double *p0, double *mu0);
+
 /* ---- solver ----------------------------------------------------------- */
 
 /* Device bytes a context for these parameters needs (for device_ws). */
@@ -179,6 +184,16 @@ lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
  * count are not changed.  Synchronises the stream. */
 lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
 
+/* Diagnostic: run nsteps time steps (the state advances as with lbm_step)
+ * with a HIP event recorded on the context's stream before and after every
+ * kernel, so each kernel is timed inside the real step sequence.  ms[k]
+ * receives the average milliseconds of kernel k and *count the number of
+ * kernels per step: 3 (row pass A, column pass B, collision pass C) or, with
+ * the split collision variant, 5 (A, B, F_x over rows, collision over row
+ * segments, density groups at the segment seams).  ms needs room for 5.
+ * Synchronises the stream. */
+lbm_status lbm_time_step_kernels(lbm_ctx *ctx, int64_t nsteps, double *ms, int *count);
+
 /* Give the fluid the velocity (vx, vy) (arrays of nx*ny, host or device per
  * src_on_device; NULL for zero): the state becomes f = feq(rho, u) with rho
  * the current density and u = v - F/(2 rho), F the force of Eq. 12 of that
@@ -187,12 +202,15 @@ lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
  * at rest in that sense rather than with zero bare velocity.  Synchronises. */
 lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int src_on_device);
 
-/* Autotuner: time the column pass of the current state for each strip width
- * (columns per workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS
- * holds and, for the factorised solve, each chunk length (column nodes per
- * thread) in {4, 8, 16}; then time the collision pass variants of
- * lbm_set_collision_variant that the mesh allows.  `repeats` launches each
- * (HIP events); keep the fastest of each for the context.  The state f is
+/* Autotuner: for each strip width of the column pass (columns per
+ * workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS holds and, for the
+ * factorised solve, each chunk length (column nodes per thread) in
+ * {4, 8, 16}, then for each collision pass variant of
+ * lbm_set_collision_variant that the mesh allows, time `repeats` whole steps
+ * (the three passes from the current state into the spare buffers, HIP
+ * events), so that every candidate meets the caches as a real step leaves
+ * them; keep the fastest of each for the context.  ms[] reports the time
+ * per step.  The state f is
  * not changed.  widths[], chunks[] and ms[] (room for 17 entries each, may be
  * NULL) receive the candidates and their average time in milliseconds --
  * column candidates as (width, chunk; chunk 0 = general reduction kernel),

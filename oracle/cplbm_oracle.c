@@ -11,6 +11,10 @@
  *
  * Everything is IEEE double precision, naive loops, no blocking or fusion.
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so cplbm_oracle.c -lm
+ * The same source built with -fopenmp runs the independent loops (lines of
+ * the compact scheme, nodes of the pointwise steps, rows of the streaming)
+ * on several threads.  Every line and node is computed by one thread in the
+ * same order as in the serial build, so the results are bitwise identical. 
  *
  * Conventions (lattice units of the mesh space, Sec. 4.1):
  *   node index  y*nx + x, x in [0,nx), y in [0,ny);
@@ -21,6 +25,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP build (n > 0 sets them); 1 for the serial build. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* ---- D2Q9 lattice (Sec. 2, text after Eq. 2) ---------------------------- */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -189,6 +208,7 @@ void orc_cfm_line(int n, double al, const double *u, double *d)
 static void cfm_rows(const orc_params *p, const double *u, double *d)
 {
     int nx = p->nx, ny = p->ny;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; y++) orc_cfm_line(nx, p->cfd_alpha, u + (size_t)y * nx, d + (size_t)y * nx);
 }
 
@@ -200,17 +220,17 @@ static void cfm_cols(const orc_params *p, const double *u, double *d)
 {
     int nx = p->nx, ny = p->ny;
     int n = p->bc_y ? 2 * ny : ny;
-    double *line = (double *)malloc(sizeof(double) * n);
-    double *dl = (double *)malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static)
     for (int x = 0; x < nx; x++) {
+        double *line = (double *)malloc(sizeof(double) * 2 * n);
+        double *dl = line + n;
         for (int y = 0; y < ny; y++) line[y] = u[(size_t)y * nx + x];
         if (p->bc_y)
             for (int y = 0; y < ny; y++) line[ny + y] = u[(size_t)(ny - 1 - y) * nx + x];
         orc_cfm_line(n, p->cfd_alpha, line, dl);
         for (int y = 0; y < ny; y++) d[(size_t)y * nx + x] = dl[y];
+        free(line);
     }
-    free(line);
-    free(dl);
 }
 
 /* Second derivative along columns: the first-derivative scheme applied twice
@@ -219,20 +239,18 @@ static void cfm_cols2(const orc_params *p, const double *u, double *d2)
 {
     int nx = p->nx, ny = p->ny;
     int n = p->bc_y ? 2 * ny : ny;
-    double *line = (double *)malloc(sizeof(double) * n);
-    double *d1 = (double *)malloc(sizeof(double) * n);
-    double *dd = (double *)malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static)
     for (int x = 0; x < nx; x++) {
+        double *line = (double *)malloc(sizeof(double) * 3 * n);
+        double *d1 = line + n, *dd = line + 2 * n;
         for (int y = 0; y < ny; y++) line[y] = u[(size_t)y * nx + x];
         if (p->bc_y)
             for (int y = 0; y < ny; y++) line[ny + y] = u[(size_t)(ny - 1 - y) * nx + x];
         orc_cfm_line(n, p->cfd_alpha, line, d1);
         orc_cfm_line(n, p->cfd_alpha, d1, dd);
         for (int y = 0; y < ny; y++) d2[(size_t)y * nx + x] = dd[y];
+        free(line);
     }
-    free(line);
-    free(d1);
-    free(dd);
 }
 
 /* Column derivative of a field as the step computes it: the first
@@ -379,6 +397,7 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
     double *dym = (double *)malloc(sizeof(double) * N);
 
     /* 1. moments (Eq. 3) */
+#pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; n++) {
         double fi[9];
         for (int i = 0; i < 9; i++) fi[i] = f[(size_t)i * N + n];
@@ -387,11 +406,13 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
     if (p->force == 1) {
         /* pseudopotential model: F = c_s^2 psi grad psi (G = -1); the mu
          * output holds psi */
+#pragma omp parallel for schedule(static)
         for (size_t n = 0; n < N; n++) o->mu[n] = orc_sc_psi(p, o->rho[n]);
         cfm_rows(p, o->mu, dxm);
         cfm_cols(p, o->mu, dym);
         cfm_rows(p, o->rho, o->dxr);
         cfm_cols(p, o->rho, o->dyr);
+#pragma omp parallel for schedule(static)
         for (size_t n = 0; n < N; n++) {
             o->fx[n] = CS2 * o->mu[n] * dxm[n];
             o->fy[n] = CS2 * o->mu[n] * dym[n];
@@ -409,6 +430,7 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
     cfm_cols(p, o->rho, o->dyr);
     cfm_cols2(p, o->rho, dyyr);
     /* 3-4. mesh chemical potential, Eq. 33: k^2 psi'(rho) - kappa lap rho */
+#pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; n++) {
         double m0 = orc_mu0_capped(p, o->rho[n]);
         o->mu[n] = p->k * p->k * m0 - p->kappa * (dxxr[n] + dyyr[n]);
@@ -417,6 +439,7 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
     cfm_rows(p, o->mu, dxm);
     cfm_cols(p, o->mu, dym);
     /* 6. nonideal force, Eq. 12: F = -rho grad mu + c_s^2 grad rho */
+#pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; n++) {
         o->fx[n] = -o->rho[n] * dxm[n] + CS2 * o->dxr[n];
         o->fy[n] = -o->rho[n] * dym[n] + CS2 * o->dyr[n];
@@ -449,6 +472,7 @@ void orc_stream(const orc_params *p, const double *fstar, const double *rho, dou
 {
     int nx = p->nx, ny = p->ny;
     size_t N = (size_t)nx * ny;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             size_t n = (size_t)y * nx + x;
@@ -487,6 +511,7 @@ void orc_step(const orc_params *p, double *f)
     alloc_fields(&o, N);
     compute_fields(p, f, &o);
     double *fs = (double *)malloc(sizeof(double) * 9 * N);
+#pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; n++) {
         double fi[9], fo[9];
         for (int i = 0; i < 9; i++) fi[i] = f[(size_t)i * N + n];

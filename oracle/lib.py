@@ -12,6 +12,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cplbm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source with OpenMP over lines and nodes (bitwise equal results)
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 EOS_VDW, EOS_RK, EOS_RKS, EOS_PR, EOS_CS = 0, 1, 2, 3, 4
 
@@ -28,26 +30,46 @@ class OracleParams(C.Structure):
 
 
 def build(force=False):
-    """Compile the oracle with gcc (IEEE order, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
+    """Compile the oracle with gcc (IEEE order, no FMA contraction): the serial
+    library and the OpenMP one."""
+    for out, extra in ((LIB, []), (LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+            tmp = out + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared"] + extra +
+                                  ["-o", tmp, SRC, "-lm"])
+            os.replace(tmp, out)
     return LIB
 
 
 _lib = None
+_libs = {}
+
+
+def threads(n=None):
+    """Switch every oracle call to the OpenMP build on n threads (n = None or
+    0: all cores), or back to the serial build (n = 1).  Returns the threads
+    the calls now use."""
+    global _lib
+    want_omp = n is None or n != 1
+    _lib = _open(LIB_OMP if want_omp else LIB)
+    return _lib.orc_threads(0 if n is None else int(n))
 
 
 def load():
     global _lib
     if _lib is None:
+        _lib = _open(LIB)
+    return _lib
+
+
+def _open(path):
+    if path not in _libs:
         build()
-        lib = C.CDLL(LIB)
+        lib = C.CDLL(path)
         d, i32, i64, P = C.c_double, C.c_int, C.c_int64, C.c_void_p
         pp = C.POINTER(OracleParams)
         for name, res, args in [
+            ("orc_threads", i32, [i32]),
             ("orc_alpha_T", d, [i32, d, d, d]),
             ("orc_p0", d, [i32, d, d, d, d, d, d]),
             ("orc_mu0", d, [i32, d, d, d, d, d, d]),
@@ -72,8 +94,8 @@ def load():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
 
 
 def _ptr(a):

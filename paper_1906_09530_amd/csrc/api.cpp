@@ -356,6 +356,23 @@ lbm_status lbm_maxwell(const lbm_params *p, double *rho_g, double *rho_l)
     return LBM_OK;
 }
 
+lbm_status lbm_eos_values(const lbm_params *p, double rho, double *p0, double *mu0)
+{
+    if (!p || p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS || !(p->a > 0 && p->b > 0 && p->R > 0))
+        return fail(nullptr, LBM_E_INVALID, "invalid EOS parameters");
+    if (!(p->T_r > 0)) return fail(nullptr, LBM_E_INVALID, "T_r must be positive");
+    const Eos e = eos_of(p);
+    long double Tc, rc, pc;
+    if (!eos_critical(e, &Tc, &rc, &pc)) return fail(nullptr, LBM_E_INVALID, "critical point not found");
+    const long double T = (long double)p->T_r * Tc;
+    const long double A = (long double)p->a * eos_alpha(e, T, Tc);
+    const long double r = rho;
+    if (!(r > 0 && r < eos_rho_max(e))) return fail(nullptr, LBM_E_DOMAIN, "rho outside the EOS domain");
+    if (p0) *p0 = (double)eos_p0(e, T, A, r);
+    if (mu0) *mu0 = (double)eos_mu0(e, T, A, r);
+    return LBM_OK;
+}
+
 size_t lbm_workspace_bytes(const lbm_params *p)
 {
     std::string why;
@@ -624,18 +641,92 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
     return LBM_OK;
 }
 
+lbm_status lbm_time_step_kernels(lbm_ctx *c, int64_t nsteps, double *ms, int *count)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (nsteps <= 0 || !ms || !count)
+        return fail(c, LBM_E_INVALID, "nsteps > 0 and outputs required");
+    const bool split = c->kp.use_iir_rows && c->kp.row_split;
+    const int K = split ? 5 : 3;
+    std::vector<hipEvent_t> ev((size_t)nsteps * (K + 1), nullptr);
+    hipError_t err = hipSuccess;
+    for (size_t i = 0; i < ev.size() && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
+    for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
+        hipEvent_t *e = &ev[(size_t)s * (K + 1)];
+        const double *fc = c->f[c->cur];
+        double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
+        err = hipEventRecord(e[0], c->stream);
+        if (err == hipSuccess) err = launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e[1], c->stream);
+        if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e[2], c->stream);
+        if (split) {
+            if (err == hipSuccess) err = launch_rows_fx_iir(c->kp, c->rho, c->mu, c->obs, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
+            if (err == hipSuccess)
+                err = launch_collide_seg_iir(c->kp, fc, c->fy, c->obs, fn, gn, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[4], c->stream);
+            if (err == hipSuccess) err = launch_group_seams(c->kp, fn, gn, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[5], c->stream);
+        } else {
+            if (err == hipSuccess)
+                err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs,
+                                          c->stream);
+            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
+        }
+        c->cur = 1 - c->cur;
+        c->steps += 1;
+    }
+    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
+    for (int k = 0; k < K; ++k) ms[k] = 0.0;
+    for (int64_t s = 0; s < nsteps && err == hipSuccess; ++s) {
+        hipEvent_t *e = &ev[(size_t)s * (K + 1)];
+        for (int k = 0; k < K && err == hipSuccess; ++k) {
+            float t = 0.f;
+            err = hipEventElapsedTime(&t, e[k], e[k + 1]);
+            ms[k] += t / (double)nsteps;
+        }
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (err != hipSuccess)
+        return fail(c, LBM_E_DEVICE, std::string("kernel timing failed: ") + hipGetErrorString(err));
+    *count = K;
+    return LBM_OK;
+}
+
 lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, double *ms,
                         int *count)
 {
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
     if (repeats <= 0) return fail(c, LBM_E_INVALID, "repeats must be positive");
-    // the column pass reads rho and d2/dx2 rho and writes mu and F_y only,
-    // so timing it repeatedly leaves the state untouched
-    HIP_OR(c, launch_rows_rho(c->kp, c->f[c->cur], c->g[c->cur], c->rho, c->mux, c->stream));
+    // Every candidate is timed inside whole steps, so that each pass meets
+    // the caches as a real step leaves them: `repeats` times pass A, the
+    // column pass and the collision pass from the current state into the
+    // spare buffers, without swapping (the state stays untouched).
     hipEvent_t e0, e1;
     HIP_OR(c, hipEventCreate(&e0));
     HIP_OR(c, hipEventCreate(&e1));
+    const double *fc = c->f[c->cur], *gc = c->g[c->cur];
+    double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
+    auto steps_ms = [&](const KParams &kp, double *avg) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int r = -1; r < repeats && e == hipSuccess; ++r) {  // r = -1: warm-up
+            if (r == 0) e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = launch_rows_rho(kp, fc, gc, c->rho, c->mux, c->stream);
+            if (e == hipSuccess) e = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
+            if (e == hipSuccess)
+                e = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        *avg = t / repeats;
+        return e;
+    };
     const int cand_w[] = {1, 2, 4, 8, 16};
     const int cand_c[] = {4, 8, 16};
     int n = 0, best_w = c->kp.cols_per_block, best_c = c->kp.col_lc;
@@ -648,16 +739,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         if (kp.cols_per_block != w) continue;  // does not fit one block
         // the general kernel ignores the chunk length: time it once
         if (!kp.use_iir_cols && ch != cand_c[0]) continue;
-        err = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
-        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < repeats && err == hipSuccess; ++r)
-            err = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
-        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float t = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-        if (err != hipSuccess) break;
-        const double avg = t / repeats;
+        double avg = 0.0;
+        if ((err = steps_ms(kp, &avg)) != hipSuccess) break;
         if (widths) widths[n] = w;
         if (chunks) chunks[n] = kp.use_iir_cols ? ch : 0;
         if (ms) ms[n] = avg;
@@ -670,27 +753,14 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     }
     if (err == hipSuccess) set_col_shape(&c->kp, best_w, best_c);
     // collision pass: populations held in registers or read twice, in one
-    // pass or split for long rows.  It reads the current f, rho, mu and F_y
-    // and writes only the spare buffers (and the scratch plane), so the state
-    // is untouched; mu and F_y are refreshed first with the chosen shape.
-    if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
+    // pass or split for long rows
     double best_row = INFINITY;
     int best_variant = c->kp.row_split ? 2 : c->kp.row_keep;
     for (int variant = 0; variant < 3 && err == hipSuccess; ++variant) {
         KParams kp = c->kp;
         if (!collision_variant(&kp, variant)) continue;
-        const double *fc = c->f[c->cur];
-        double *fn = c->f[1 - c->cur], *gn = c->g[1 - c->cur];
-        err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
-        if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-        for (int r = 0; r < repeats && err == hipSuccess; ++r)
-            err = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
-        if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float t = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-        if (err != hipSuccess) break;
-        const double avg = t / repeats;
+        double avg = 0.0;
+        if ((err = steps_ms(kp, &avg)) != hipSuccess) break;
         if (widths) widths[n] = 0;
         if (chunks) chunks[n] = variant;
         if (ms) ms[n] = avg;

@@ -145,5 +145,12 @@ bool iir_split_ok(const KParams &p);
 hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
                                     const double *mu, const double *fy, double *fx,
                                     double *fout, double *gout, hipStream_t s);
+// The three kernels of the split pass, one launch each (the timing path
+// brackets each with events).
+hipError_t launch_rows_fx_iir(const KParams &p, const double *rho, const double *mu, double *fx,
+                              hipStream_t s);
+hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const double *fy,
+                                  const double *fx, double *fout, double *gout, hipStream_t s);
+hipError_t launch_group_seams(const KParams &p, const double *fout, double *gout, hipStream_t s);
 
 }  // namespace cplbm

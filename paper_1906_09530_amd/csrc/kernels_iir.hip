@@ -233,7 +233,10 @@ __device__ __forceinline__ Chunk<LC> seg_chunk(const KParams &p)
 // Pass A on rows [y0, y0 + rows_per_block) of one mesh: rho, and the row part
 // of the chemical potential of Eq. 33, k^2 psi'(rho) - kappa d2rho/dx2.
 // rho comes from the state's three density groups g (written by the previous
-// collision pass): rho = (g0 + g1) + g2.
+// collision pass): rho = (g0 + g1) + g2.  SC: the pseudopotential model,
+// whose plane holds psi instead (a template argument, so that the
+// chemical-potential kernel carries none of its arithmetic).
+template <bool SC = false>
 __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const double *__restrict__ g,
                                               double *__restrict__ rho_out,
                                               double *__restrict__ mux_out)
@@ -261,11 +264,11 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k)
-            mx[k] = p.sc ? sc_psi(p, rho[k]) : p.k2 * mu0_capped(p, rho[k]);
+            mx[k] = SC ? sc_psi(p, rho[k]) : p.k2 * mu0_capped(p, rho[k]);
     }
     // uniform: the Laplacian is not used (kappa = 0), or the pseudopotential
     // model, whose plane holds psi
-    if (p.kappa_zero || p.sc) {
+    if (p.kappa_zero || SC) {
         if (m.ok) vstore<LC>(mux_out + base, mx);
         return;
     }
@@ -279,12 +282,12 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     }
 }
 
-template <int MAXT>
+template <int MAXT, bool SC>
 __global__ __launch_bounds__(MAXT) void k_rows_rho_iir(KParams p, const double *__restrict__ g,
                                                        double *__restrict__ rho_out,
                                                        double *__restrict__ mux_out)
 {
-    rows_rho_body(p, blockIdx.x * p.rows_per_block, g, rho_out, mux_out);
+    rows_rho_body<SC>(p, blockIdx.x * p.rows_per_block, g, rho_out, mux_out);
 }
 
 __device__ __forceinline__ int strip_of_block(const KParams &p)
@@ -808,7 +811,10 @@ __global__ __launch_bounds__(256) void kb_rows_rho(const KParams *__restrict__ k
 {
     const WorkItem w = work[blockIdx.x];
     const SimBuffers &b = sb[w.sim];
-    rows_rho_body(kps[w.sim], w.start, b.g[parity], b.rho, b.mux);
+    if (kps[w.sim].sc)  // uniform over the workgroup
+        rows_rho_body<true>(kps[w.sim], w.start, b.g[parity], b.rho, b.mux);
+    else
+        rows_rho_body<false>(kps[w.sim], w.start, b.g[parity], b.rho, b.mux);
 }
 
 template <int LC, int MAXT>
@@ -934,7 +940,10 @@ hipError_t launch_rows_rho_iir(const KParams &p, const double *g, double *rho, d
 {
     const int T = row_threads_iir(p);
 #define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, g, rho, mux
-    CPLBM_IIR_THREADS(T, k_rows_rho_iir<256>, k_rows_rho_iir<1024>, ARGS);
+    if (p.sc)
+        CPLBM_IIR_THREADS(T, (k_rows_rho_iir<256, true>), (k_rows_rho_iir<1024, true>), ARGS);
+    else
+        CPLBM_IIR_THREADS(T, (k_rows_rho_iir<256, false>), (k_rows_rho_iir<1024, false>), ARGS);
 #undef ARGS
     return hipGetLastError();
 }
@@ -959,17 +968,19 @@ bool iir_split_ok(const KParams &p)
            p.seg_len % kRowLC == 0 && p.seg_len <= kSegLen && p.nx / p.seg_len >= 2;
 }
 
-hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
-                                    const double *mu, const double *fy, double *fx,
-                                    double *fout, double *gout, hipStream_t s)
+hipError_t launch_rows_fx_iir(const KParams &p, const double *rho, const double *mu, double *fx,
+                              hipStream_t s)
 {
-    if (!iir_split_ok(p)) return hipErrorInvalidValue;
     const int T = row_threads_iir(p);
 #define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, rho, mu, fx
     CPLBM_IIR_THREADS(T, k_rows_fx_iir<256>, k_rows_fx_iir<1024>, ARGS);
 #undef ARGS
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const double *fy,
+                                  const double *fx, double *fout, double *gout, hipStream_t s)
+{
     const int S = p.seg_len, blocks = p.ny * (p.nx / S);
     const size_t lds = line_lds(S, 1, kRowLC, true);
 #define ARGS dim3(blocks), dim3(S / kRowLC), lds, s, p, f, fy, fx, fout, gout
@@ -982,11 +993,26 @@ hipError_t launch_collide_split_iir(const KParams &p, const double *f, const dou
     else
         hipLaunchKernelGGL((k_collide_seg_iir<false, false>), ARGS);
 #undef ARGS
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t seams = (size_t)p.ny * (p.nx / S) * 2;
-    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
-                       (const double *)fout, gout);
     return hipGetLastError();
+}
+
+hipError_t launch_group_seams(const KParams &p, const double *fout, double *gout, hipStream_t s)
+{
+    const size_t seams = (size_t)p.ny * (p.nx / p.seg_len) * 2;
+    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
+                       fout, gout);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
+                                    const double *mu, const double *fy, double *fx,
+                                    double *fout, double *gout, hipStream_t s)
+{
+    if (!iir_split_ok(p)) return hipErrorInvalidValue;
+    hipError_t e = launch_rows_fx_iir(p, rho, mu, fx, s);
+    if (e == hipSuccess) e = launch_collide_seg_iir(p, f, fy, fx, fout, gout, s);
+    if (e == hipSuccess) e = launch_group_seams(p, fout, gout, s);
+    return e;
 }
 
 hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,

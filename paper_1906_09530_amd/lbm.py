@@ -88,6 +88,8 @@ def load():
         "lbm_get_state": (i32, [P, P, i32]),
         "lbm_set_state": (i32, [P, P, i32]),
         "lbm_time_passes": (i32, [P, i64, pd]),
+        "lbm_time_step_kernels": (i32, [P, i64, pd, C.POINTER(C.c_int)]),
+        "lbm_eos_values": (i32, [pp, d, pd, pd]),
         "lbm_autotune": (i32, [P, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), pd,
                             C.POINTER(C.c_int)]),
         "lbm_set_column_shape": (i32, [P, i32, i32]),
@@ -154,6 +156,13 @@ def maxwell(p):
     g, l = C.c_double(), C.c_double()
     _check(load().lbm_maxwell(C.byref(p), C.byref(g), C.byref(l)))
     return g.value, l.value
+
+
+def eos_values(p, rho):
+    """(p0(rho), psi'(rho)) at p.T_r, momentum units (Eqs. 14-21)."""
+    a, b = C.c_double(), C.c_double()
+    _check(load().lbm_eos_values(C.byref(p), float(rho), C.byref(a), C.byref(b)))
+    return a.value, b.value
 
 
 def workspace_bytes(p):
@@ -257,6 +266,14 @@ class Solver:
         out = (C.c_double * 3)()
         _check(load().lbm_time_passes(self.ctx, int(n), out), self.ctx)
         return list(out)
+
+    def time_step_kernels(self, n):
+        """Average ms of each kernel over n real steps (events around every
+        launch inside the sequence); 3 kernels, or 5 with the split pass."""
+        ms = (C.c_double * 5)()
+        cnt = C.c_int()
+        _check(load().lbm_time_step_kernels(self.ctx, int(n), ms, C.byref(cnt)), self.ctx)
+        return list(ms)[:cnt.value]
 
     def autotune(self, repeats=20):
         """Pick the fastest column-pass shape; returns {(width, chunk): ms}

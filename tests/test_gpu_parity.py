@@ -10,6 +10,7 @@ and column passes with ragged last blocks; the full-size cases check one step
 of the benchmark and splash workloads over the whole field.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -468,3 +469,42 @@ def test_mu_limit_binds_at_seeded_nodes(cap):
     m = oracle.mu0_capped(raw, rho0.ravel())
     assert (m >= cap).sum() >= 3
     _run_case("pr-limit%g" % cap, p, op, rho0, ux0, uy0, [1, 20, 100, 300])
+
+
+def _fullsize_case(name):
+    """GPU parameters and initial fields of the full-size cases written by
+    tests/golden/make_fullsize.py (same recipe, oracle-side coexistence
+    densities)."""
+    if name == "pr1024":
+        p = lbm.params(lbm.EOS_PR, 0.5, 1024, 1024, kappa=0.004, tau=0.8, k=0.1, mu_cap=6.0)
+        g, l = A.coexistence(A.EOS_PR, 0.5)
+        return p, inputs.droplet(1024, 1024, g, l, 200.0, 10.0)
+    p = lbm.params(lbm.EOS_CS, 0.6, 4096, 2048, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0, bc_y=1)
+    g, l = A.coexistence(A.EOS_CS, 0.6)
+    return p, inputs.splash(4096, 2048, g, l, 100.0, 5.0, film=40, drop_uy=-0.05)
+
+
+@pytest.mark.parametrize("name", ["pr1024", "cs4096x2048walls"])
+def test_full_size_1000_steps(name, golden_dir):
+    """The benchmark drop (1024^2 PR, T_r = 0.5, limit 6) and the 4096 x 2048
+    CS splash between walls after 1000 steps, autotuned as the benchmark
+    runs them, against the oracle's fields at the centre row, the centre
+    column and 2048 seeded nodes (tests/golden/make_fullsize.py, OpenMP
+    oracle).  Bar: 1e-10 relative on rho, 1e-10 of the field's max |v| on v."""
+    import torch
+    gold = np.load(os.path.join(golden_dir, "fullsize_%s.npz" % name))
+    p, (rho0, ux0, uy0) = _fullsize_case(name)
+    assert (p.nx, p.ny) == (int(gold["nx"]), int(gold["ny"]))
+    print("\n[case] %s %dx%d 1000 steps (autotuned)" % (name, p.nx, p.ny), flush=True)
+    d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+    s = lbm.Solver(p, *d)
+    s.autotune(3)
+    s.step(int(gold["steps"]))
+    r, vx, vy = s.moments()
+    s.close()
+    idx = gold["idx"]
+    er = float(np.max(np.abs(r.ravel()[idx] - gold["rho"]) / np.abs(gold["rho"])))
+    ev = float(max(np.abs(vx.ravel()[idx] - gold["vx"]).max(),
+                   np.abs(vy.ravel()[idx] - gold["vy"]).max()) / float(gold["vmax"]))
+    print("  %d nodes: rel err rho %.2e, v %.2e" % (len(idx), er, ev), flush=True)
+    assert er <= TOL and ev <= TOL

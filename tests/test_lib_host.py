@@ -131,3 +131,21 @@ def test_batch_validates_each_simulation():
     assert st == lbm.LBM_E_DOMAIN and "simulation 1" in msg
     st, _ = _batch_status([], [])
     assert st == lbm.LBM_E_INVALID
+
+
+@pytest.mark.parametrize("eos,T_r", [(0, 0.6), (1, 0.8), (2, 0.5), (3, 0.5), (4, 0.7)])
+def test_eos_values_match_oracle(eos, T_r):
+    """lbm_eos_values (host long double) against the oracle's mpmath EOS."""
+    p = lbm.params(eos, T_r, 16, 16, kappa=0.0, tau=1.0, k=1.0)
+    e = A.EOS(eos)
+    T, al = e.temperature(T_r)
+    g, l = e.maxwell(T_r)
+    for r in (float(g), 0.5 * float(g + l), float(l)):
+        p0, mu0 = lbm.eos_values(p, r)
+        # p0 is a difference of two terms that nearly cancel on the liquid
+        # branch: compare on the scale of the repulsive term
+        scale = abs(float(r * e.R * T / (1 - e.b * r)))
+        assert abs(p0 - float(e.p0(mp.mpf(r), T, al))) <= 1e-13 * scale
+        assert mu0 == pytest.approx(float(e.mu0(mp.mpf(r), T, al)), rel=1e-12, abs=1e-15)
+    with pytest.raises(lbm.LBMError):
+        lbm.eos_values(p, float(e.rho_max()) * 1.01)

@@ -274,3 +274,27 @@ def test_flat_interface_exact_discrete_momentum_balance():
     jump = mu[0] - mu[64]
     k2dmu = k * k * float(e.mu0(mp.mpf(float(r[0])), T, al) - e.mu0(mp.mpf(g), T, al))
     assert jump > 0 and k2dmu == pytest.approx(jump, rel=0.05)
+
+
+@pytest.mark.parametrize("walls,collision,force", [(0, 0, 0), (1, 1, 0), (1, 0, 1)])
+def test_openmp_build_is_bitwise_serial(walls, collision, force):
+    """The OpenMP build of the oracle (lines and nodes spread over threads)
+    gives the serial build's state bit for bit."""
+    if force == 0:
+        p = A.params(A.EOS_PR, 0.6, 96, 80, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0, bc_y=walls,
+                     collision=collision, rates=(1.64, 1.54, 1.2))
+        g, l = A.coexistence(A.EOS_PR, 0.6)
+    else:
+        p = A.params(A.EOS_CS, 0.7, 96, 80, kappa=0.0, tau=1.0, k=0.3, bc_y=walls, force=1)
+        g, l = A.coexistence(A.EOS_CS, 0.7)
+    rho, ux, uy = inputs.droplet(96, 80, g, l, 20.0, 5.0, seed=3, noise=1e-6)
+    try:
+        oracle.threads(1)
+        f1 = oracle.init(p, rho, ux, uy)
+        oracle.run(p, f1, 40)
+        assert oracle.threads(4) == 4
+        f2 = oracle.init(p, rho, ux, uy)
+        oracle.run(p, f2, 40)
+    finally:
+        oracle.threads(1)
+    np.testing.assert_array_equal(f1, f2)
