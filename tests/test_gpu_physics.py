@@ -243,3 +243,166 @@ def test_spurious_current_of_converged_drops():
             assert ratio > 1e4
     for eos in (lbm.EOS_PR, lbm.EOS_RKS):
         assert vmax[(eos, 0.4)] > vmax[(eos, 0.5)] > vmax[(eos, 0.6)]
+
+
+def _line_width_and_sigma(p, op, f, r):
+    """Interface width (rho_l - rho_g) / max |d rho/dy| and surface tension of a
+    converged flat slab along one column: Eq. 10's kappa (d rho/dy)^2 and the
+    lattice's F_y^2/(4 rho), summed over the column and halved (two
+    interfaces).  The derivative and force come from the oracle on the GPU's
+    state."""
+    import oracle
+    col = r[:, 0]
+    dy = oracle.cfm_columns(op, r)[:, 0]
+    _, _, _, _, _, fy = oracle.moments(op, np.ascontiguousarray(f), want_force=True)
+    width = (col.max() - col.min()) / np.abs(dy).max()
+    s10 = p.kappa * float(np.sum(dy ** 2)) / 2
+    sff = float(np.sum(fy[:, 0] ** 2 / (4 * col))) / 2
+    return width, s10, sff
+
+
+# Figs. 6-7: six EOS at T/Tc = 0.6 (PRM: Peng-Robinson for methane); kappa
+# fixed per EOS (a 4-node interface at k = 0.3; 3 nodes for van der Waals,
+# whose liquid is denser and less stable), k = 0.05 ... 0.2
+F67_EOS = [("VdW", lbm.EOS_VDW, 0.344, 3.0), ("RK", lbm.EOS_RK, 0.344, 4.0),
+           ("RKS", lbm.EOS_RKS, 0.344, 4.0), ("PR", lbm.EOS_PR, 0.344, 4.0),
+           ("PRM", lbm.EOS_PR, 0.011, 4.0), ("CS", lbm.EOS_CS, 0.344, 4.0)]
+F67_K = (0.05, 0.1, 0.15, 0.2)
+
+
+def test_interface_width_and_surface_tension_vs_k():
+    """Sec. 5.2, Figs. 6-7: flat slabs of six EOS at T/Tc = 0.6 in mesh spaces
+    k = 0.05 ... 0.2 at a fixed kappa per EOS.  The interface width in nodes
+    goes as 1/k: width * k (the momentum-space width) is the same for every
+    k to 8 %; the surface tension of the lattice divided by k (its
+    momentum-space value) likewise.  Both exceed the continuum w1 sqrt(kappa)
+    and sqrt(kappa) sigma1: the forced lattice's normal flux F^2/(4 rho) acts
+    as an extra gradient coefficient of order c_s^4/(2 rho) (see the design
+    notes); the measured values are printed."""
+    T_r = 0.6
+    cases, ps, r0, ops = [], [], [], []
+    for name, eos, om, nodes in F67_EOS:
+        e = A.EOS(eos, omega=om)
+        it = e.interface(T_r)
+        w1, s1 = float(mp.re(it["width1"])), float(mp.re(it["sigma1"]))
+        g, l = (float(v) for v in e.maxwell(T_r))
+        kap = (nodes * 0.3 / w1) ** 2
+        for k in F67_K:
+            w = w1 * kap ** 0.5 / k
+            ny = 384 if k < 0.1 else 256
+            cases.append((name, k, kap, w1, s1))
+            ps.append(lbm.params(eos, T_r, 64, ny, kappa=kap, tau=1.0, k=k, omega=om))
+            ops.append(A.params(eos, T_r, 64, ny, kappa=kap, tau=1.0, k=k, omega=om))
+            r0.append(inputs.slab(64, ny, g, l, min(w, 16.0))[0])
+    b = lbm.Batch(ps, r0)
+    _converge(b, len(ps), max_chunks=40)
+    print("\n EOS   k     width   width*k  w1 sqrt(kappa)  sigma_Eq10/k  sigma_lattice/k  "
+          "sqrt(kappa) sigma1")
+    res = {}
+    for i, (name, k, kap, w1, s1) in enumerate(cases):
+        r = b.moments(i)[0]
+        width, s10, sff = _line_width_and_sigma(ps[i], ops[i], b.get_state(i), r)
+        res.setdefault(name, []).append((width * k, (s10 + sff) / k, s10 / k))
+        print(" %-4s %.2f  %6.2f   %.3f    %.3f           %.3e     %.3e        %.3e" % (
+            name, k, width, width * k, w1 * kap ** 0.5, s10 / k, (s10 + sff) / k,
+            kap ** 0.5 * s1), flush=True)
+    for name, vals in res.items():
+        wk = [v[0] for v in vals]
+        sk = [v[1] for v in vals]
+        assert max(wk) / min(wk) - 1 <= 0.08, (name, wk)
+        assert max(sk) / min(sk) - 1 <= 0.08, (name, sk)
+
+
+def test_pseudopotential_against_chemical_potential_slabs():
+    """Sec. 5.1, Fig. 4: CS flat slabs, 64 x 256, k = 0.2, tau = 1, with the
+    pseudopotential force (no kappa) and with the chemical-potential force
+    (8-node interface), T/Tc = 0.5 ... 0.8.  Both keep the liquid within 1e-4
+    of Maxwell; the gas of both settles above it, the pseudopotential's
+    further (measured 2-5x), so the chemical-potential model stays closer to
+    the Maxwell curve at every temperature, as the paper reports."""
+    temps = (0.5, 0.6, 0.7, 0.8)
+    k, W = 0.2, 8.0
+    ps, r0, ml = [], [], []
+    e = A.EOS(A.EOS_CS)
+    for force in (lbm.FORCE_SC, lbm.FORCE_CP):
+        for T_r in temps:
+            g, l = A.coexistence(A.EOS_CS, T_r)
+            w1 = float(mp.re(e.interface(T_r)["width1"]))
+            kap = 0.0 if force == lbm.FORCE_SC else (W * k / w1) ** 2
+            ps.append(lbm.params(lbm.EOS_CS, T_r, 64, 256, kappa=kap, tau=1.0, k=k, force=force))
+            r0.append(inputs.slab(64, 256, g, l, 4.0)[0])
+            ml.append((g, l))
+    b = lbm.Batch(ps, r0)
+    _converge(b, len(ps), max_chunks=40)
+    print("\n force  T/Tc  rho_l-Maxwell  rho_g-Maxwell")
+    off = {}
+    for i, p in enumerate(ps):
+        r = b.moments(i)[0]
+        g, l = ml[i]
+        dl, dg = r[128, 0] / l - 1, r[0, 0] / g - 1
+        name = "SC" if p.force == lbm.FORCE_SC else "CP"
+        off[(name, p.T_r)] = dg
+        print(" %s     %.1f   %+.2e      %+.2e" % (name, p.T_r, dl, dg), flush=True)
+        assert abs(dl) <= 1e-4
+        assert dg > 0
+    for T_r in temps:
+        assert off[("SC", T_r)] > off[("CP", T_r)]
+
+
+def _spreading(Re, k, W, collision, rates, steps=3600):
+    """A drop of diameter D = 100 falling at U = 0.1 onto a film 30 nodes
+    thick in a 1000 x 300 box between walls (Sec. 5.5: PR, T/Tc = 0.6,
+    limit 6, tau from Re = U D / nu); the spreading radius r is half the
+    width of the liquid run through the impact point on the row two nodes
+    above the film, at t* = U (t - t_impact) / D."""
+    nx, ny, D, U, film = 1000, 300, 100.0, 0.1, 30
+    tau = 3 * U * D / Re + 0.5
+    w1 = float(mp.re(A.EOS(A.EOS_PR).interface(0.6)["width1"]))
+    g, l = A.coexistence(A.EOS_PR, 0.6)
+    p = lbm.params(lbm.EOS_PR, 0.6, nx, ny, kappa=(W * k / w1) ** 2, tau=tau, k=k, mu_cap=6.0,
+                   bc_y=1, collision=collision, rates=rates)
+    y0 = film + D / 2 + 5.0
+    rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, D / 2, W, film=film, drop_center=(nx / 2, y0),
+                                   drop_uy=-U)
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    t_imp = (y0 - D / 2 - film) / U
+    half = 0.5 * (g + l)
+    pts = []
+    for n in range(100, steps + 1, 100):
+        s.step(100)
+        row = s.moments()[0][film + 2, :]
+        assert np.isfinite(row).all()
+        liq = row > half
+        c = nx // 2
+        if not liq[c]:
+            continue
+        a, b = c, c
+        while a > 0 and liq[a - 1]:
+            a -= 1
+        while b < nx - 1 and liq[b + 1]:
+            b += 1
+        pts.append((U * (n - t_imp) / D, (b - a + 1) / 2.0 / D))
+    s.close()
+    return pts
+
+
+@pytest.mark.parametrize("Re,k,W,collision,rates", [
+    (40, 0.1, 6.0, lbm.COLLISION_BGK, lbm.MRT_RATES),
+    (150, 0.1, 8.0, lbm.COLLISION_MRT, (1.64, 1.54, 1.2))])
+def test_drop_spreading_law(Re, k, W, collision, rates):
+    """Sec. 5.5, Fig. 11: after impact the spreading radius follows
+    r/D ~ C sqrt(U t / D) with C near 1.3 (the two-dimensional value the
+    paper quotes).  Measured C = (r/D)/sqrt(t*) over t* = 0.5 ... 1.5 lies in
+    1.25 ... 1.5 at Re = 40 (BGK) and Re = 150 (MRT), and the power-law
+    exponent fitted over t* = 0.1 ... 1.5 in 0.55 ... 0.7.  Re = 400 (the
+    paper's Fig. 14) diverges in the first 100 steps with every setting tried
+    (BGK and MRT, k = 0.05 and 0.1, limit 6)."""
+    pts = _spreading(Re, k, W, collision, rates)
+    C = [r / np.sqrt(t) for t, r in pts if 0.5 <= t <= 1.5]
+    sel = [(t, r) for t, r in pts if 0.1 <= t <= 1.5]
+    expo, logc = np.polyfit(np.log([t for t, _ in sel]), np.log([r for _, r in sel]), 1)
+    print("\nRe %d: t* r/D: %s" % (Re, " ".join("%.2f:%.3f" % q for q in pts[1:24:3])))
+    print("Re %d: C over t* 0.5-1.5: %.3f ... %.3f; fit exponent %.3f, C %.3f" % (
+        Re, min(C), max(C), expo, np.exp(logc)), flush=True)
+    assert 1.2 <= min(C) and max(C) <= 1.55
+    assert 0.5 <= expo <= 0.72
