@@ -18,7 +18,7 @@ Two parts:
   density field.
 """
 from .lib import (  # noqa: F401
-    EOS_CS, EOS_PR, EOS_RK, EOS_RKS, EOS_VDW, OracleParams, build, cfm_columns, cfm_line, collide_node,
+    EOS_CS, EOS_PR, EOS_RK, EOS_RKS, EOS_VDW, OracleParams, build, cfm_columns, cfm_columns_wall_value, cfm_line, collide_node,
     collide_node_mrt, feq, init, load, moments, mrt_inverse, mrt_matrix, mu0, mu0_capped, p0,
     alpha_T, run, run_until_converged, sc_psi, step, stream, threads,
 )

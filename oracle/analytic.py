@@ -250,18 +250,20 @@ MRT_RATES = (1.64, 1.54, 1.9)
 
 def params(eos, T_r, nx, ny, *, kappa, tau, k, mu_cap=float("inf"), cfd_alpha=1.0 / 3.0,
            bc_y=0, wall_ux=0.0, omega=None, a=None, b=None, R=1, collision=0, force=0,
-           rates=MRT_RATES):
+           rates=MRT_RATES, wetting=0, mu_wall=0.0):
     """OracleParams for the C oracle, with T = T_r T_c and alpha(T) from this
     module's critical point.  collision: 0 BGK (Eq. 1), 1 MRT (Eq. 4) with
     rates (s_e, s_eps, s_q); force: 0 chemical potential (Eq. 12), 1
-    pseudopotential comparison model (Sec. 5.1)."""
+    pseudopotential comparison model (Sec. 5.1); wetting: walls hold the
+    chemical potential at mu_wall (momentum units) instead of the
+    neighbour-node value."""
     e = EOS(eos, a=a, b=b, R=R, omega=OMEGA_WATER if omega is None else omega)
     T, al = e.temperature(T_r)
     return OracleParams(nx=nx, ny=ny, bc_y=bc_y, eos=eos, wall_ux=wall_ux, a=float(e.a),
                         b=float(e.b), R=float(e.R), T=float(T), alpha_T=float(al),
                         kappa=kappa, tau=tau, k=k, mu_cap=mu_cap, cfd_alpha=cfd_alpha,
                         collision=collision, force=force, s_e=rates[0], s_eps=rates[1],
-                        s_q=rates[2])
+                        s_q=rates[2], wetting=wetting, mu_wall=mu_wall)
 
 
 @functools.lru_cache(maxsize=None)

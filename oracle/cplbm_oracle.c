@@ -68,6 +68,8 @@ typedef struct {
     int32_t collision; /* 0: BGK (Eq. 1); 1: MRT (Eq. 4) */
     int32_t force;     /* 0: chemical potential (Eq. 12); 1: pseudopotential (Sec. 5.1) */
     double s_e, s_eps, s_q;  /* MRT relaxation rates (Eq. 4); s_v = 1/tau */
+    int32_t wetting;   /* walls: 0 neighbour-node chemical potential; 1 prescribed */
+    double mu_wall;    /* prescribed wall chemical potential, momentum units */
 } orc_params;
 
 /* Temperature functions of the RK, RKS and PR EOS (Eqs. 16 and 18). */
@@ -233,6 +235,26 @@ static void cfm_cols(const orc_params *p, const double *u, double *d)
     }
 }
 
+/* d/dy of the chemical potential between walls that hold it at a prescribed
+ * value u_w (the chemical-potential boundary condition of a wetting wall,
+ * Sec. 5.5 and its ref. [45]): the column of u - u_w is extended oddly about
+ * the two wall planes (length 2 ny), so that u takes the value u_w on the
+ * walls, and differentiated as one periodic line. */
+static void cfm_cols_wall_value(const orc_params *p, const double *u, double u_w, double *d)
+{
+    int nx = p->nx, ny = p->ny, n = 2 * ny;
+#pragma omp parallel for schedule(static)
+    for (int x = 0; x < nx; x++) {
+        double *line = (double *)malloc(sizeof(double) * 2 * n);
+        double *dl = line + n;
+        for (int y = 0; y < ny; y++) line[y] = u[(size_t)y * nx + x] - u_w;
+        for (int y = 0; y < ny; y++) line[ny + y] = -(u[(size_t)(ny - 1 - y) * nx + x] - u_w);
+        orc_cfm_line(n, p->cfd_alpha, line, dl);
+        for (int y = 0; y < ny; y++) d[(size_t)y * nx + x] = dl[y];
+        free(line);
+    }
+}
+
 /* Second derivative along columns: the first-derivative scheme applied twice
  * (Sec. 4.3).  Between walls both applications act on the extended line. */
 static void cfm_cols2(const orc_params *p, const double *u, double *d2)
@@ -262,6 +284,12 @@ void orc_cfm_columns(const orc_params *p, const double *u, double *d, int second
         cfm_cols2(p, u, d);
     else
         cfm_cols(p, u, d);
+}
+
+/* The same for a field held at u_w on the walls (odd extension of u - u_w). */
+void orc_cfm_columns_wall_value(const orc_params *p, const double *u, double u_w, double *d)
+{
+    cfm_cols_wall_value(p, u, u_w, d);
 }
 
 /* ---- lattice Boltzmann pieces (Sec. 2) ---------------------------------- */
@@ -435,9 +463,13 @@ static void compute_fields(const orc_params *p, const double *f, fields *o)
         double m0 = orc_mu0_capped(p, o->rho[n]);
         o->mu[n] = p->k * p->k * m0 - p->kappa * (dxxr[n] + dyyr[n]);
     }
-    /* 5. gradient of the chemical potential */
+    /* 5. gradient of the chemical potential (between wetting walls the wall
+     *    holds the prescribed value, k^2 mu_wall on the mesh) */
     cfm_rows(p, o->mu, dxm);
-    cfm_cols(p, o->mu, dym);
+    if (p->bc_y && p->wetting)
+        cfm_cols_wall_value(p, o->mu, p->k * p->k * p->mu_wall, dym);
+    else
+        cfm_cols(p, o->mu, dym);
     /* 6. nonideal force, Eq. 12: F = -rho grad mu + c_s^2 grad rho */
 #pragma omp parallel for schedule(static)
     for (size_t n = 0; n < N; n++) {

@@ -26,6 +26,7 @@ class OracleParams(C.Structure):
         ("tau", C.c_double), ("k", C.c_double), ("mu_cap", C.c_double),
         ("cfd_alpha", C.c_double), ("collision", C.c_int32), ("force", C.c_int32),
         ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
+        ("wetting", C.c_int32), ("mu_wall", C.c_double),
     ]
 
 
@@ -76,6 +77,7 @@ def _open(path):
             ("orc_mu0_capped", d, [pp, d]),
             ("orc_cfm_line", None, [i32, d, P, P]),
             ("orc_cfm_columns", None, [pp, P, P, i32]),
+            ("orc_cfm_columns_wall_value", None, [pp, P, d, P]),
             ("orc_feq", d, [i32, d, d, d]),
             ("orc_node_moments", None, [P, P, P, P]),
             ("orc_collide_node", None, [P, d, d, d, d, d, d, P]),
@@ -139,6 +141,16 @@ def cfm_columns(p, u, second=False):
     u = np.ascontiguousarray(u, dtype=np.float64)
     d = np.empty_like(u)
     load().orc_cfm_columns(C.byref(p), _ptr(u), _ptr(d), int(second))
+    return d
+
+
+def cfm_columns_wall_value(p, u, u_w):
+    """d/dy of the field u[ny][nx] held at u_w on the walls (odd extension of
+    u - u_w), as the oracle's step differentiates the chemical potential
+    between wetting walls."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    d = np.empty_like(u)
+    load().orc_cfm_columns_wall_value(C.byref(p), _ptr(u), float(u_w), _ptr(d))
     return d
 
 

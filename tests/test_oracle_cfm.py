@@ -134,3 +134,34 @@ def test_wall_columns_closed_form(al, ny):
         ext = np.concatenate([u[:, x], u[::-1, x]])
         ref = np.linalg.solve(L, Rm @ ext)[:ny]
         np.testing.assert_allclose(oracle.cfm_columns(p, u)[:, x], ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("al", [1 / 3, 1 / 4])
+@pytest.mark.parametrize("ny", [16, 40])
+def test_wetting_wall_columns_closed_form(al, ny):
+    """A wetting wall holds the chemical potential at its value u_w: the
+    column of u - u_w is extended oddly about both wall planes.
+    u(y) = u_w + sin(theta (y + 1/2)), theta = pi m / ny, is odd about both
+    walls around u_w, so its extension is one Fourier mode of the 2 ny line
+    and the scheme returns exactly k'(theta) cos(theta (y + 1/2)); a random
+    column matches the dense solve of the explicitly extended line."""
+    from oracle import analytic as A
+    a, b = 2 * (al + 2) / 3, (4 * al - 1) / 3
+    nx, u_w = 3, 0.37
+    p = A.params(A.EOS_CS, 0.7, nx, ny, kappa=0.0, tau=1.0, k=1.0, cfd_alpha=al, bc_y=1,
+                 wetting=1, mu_wall=u_w)
+    y = np.arange(ny)
+    for m in [1, 2, ny // 2, ny - 1]:
+        th = np.pi * m / ny
+        kp = (a * np.sin(th) + b / 2 * np.sin(2 * th)) / (1 + 2 * al * np.cos(th))
+        ph = np.pi * ((m * (2 * y + 1)) % (4 * ny)) / (2 * ny)
+        u = np.repeat((u_w + np.sin(ph))[:, None], nx, axis=1)
+        d = oracle.cfm_columns_wall_value(p, u, u_w)
+        np.testing.assert_allclose(d[:, 1], kp * np.cos(ph), rtol=0, atol=4e-14)
+    u = np.random.default_rng(ny + 1).standard_normal((ny, nx))
+    L, Rm = _dense(2 * ny, al, a, b)
+    for x in range(nx):
+        ext = np.concatenate([u[:, x] - u_w, -(u[::-1, x] - u_w)])
+        ref = np.linalg.solve(L, Rm @ ext)[:ny]
+        np.testing.assert_allclose(oracle.cfm_columns_wall_value(p, u, u_w)[:, x], ref,
+                                   rtol=0, atol=1e-13)
