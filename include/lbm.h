@@ -92,6 +92,13 @@ typedef struct {
                                 moments, each in (0, 2) (Eq. 4; the paper uses 1.64,
                                 1.54, 1.9); the stress moments relax at 1/tau.
                                 Ignored by BGK. */
+    int32_t wetting;    /* walls (bc_y = 1) only: 0 the neighbour-node chemical-potential
+                           condition of Sec. 5.5 (mu on the far side of a wall mirrors the
+                           fluid, zero normal derivative); 1 a wetting wall that holds mu at
+                           k^2 mu_wall (the chemical-potential boundary of ref. [45]; mu is
+                           extended oddly about the wall value).  Chemical-potential force
+                           only. */
+    double mu_wall;     /* wall chemical potential, momentum units (as psi') */
 } lbm_params;
 
 /* Collision operator (Sec. 2). */

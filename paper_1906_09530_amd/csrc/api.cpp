@@ -109,6 +109,11 @@ lbm_status validate(const lbm_params *p, std::string *why)
         return bad("collision must be LBM_COLLISION_BGK or LBM_COLLISION_MRT");
     if (p->force != LBM_FORCE_CP && p->force != LBM_FORCE_SC)
         return bad("force must be LBM_FORCE_CP or LBM_FORCE_SC");
+    if (p->wetting != 0 && p->wetting != 1) return bad("wetting must be 0 or 1");
+    if (p->wetting && !p->bc_y) return bad("wetting walls need bc_y = 1");
+    if (p->wetting && p->force != LBM_FORCE_CP)
+        return bad("wetting walls act on the chemical potential (LBM_FORCE_CP)");
+    if (p->wetting && !finite(p->mu_wall)) return bad("mu_wall must be finite");
     if (p->collision == LBM_COLLISION_MRT) {
         for (double r : {p->s_e, p->s_eps, p->s_q})
             if (!(finite(r) && r > 0 && r < 2)) return bad("MRT rates must lie in (0, 2)");
@@ -154,6 +159,8 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     k.mu_cap = p->mu_cap;
     k.wall_ux = p->wall_ux;
     k.sc = p->force == LBM_FORCE_SC;
+    k.wet = p->bc_y && p->wetting;
+    k.mu_wall = k.wet ? p->k * p->k * p->mu_wall : 0.0;
     k.mrt = p->collision == LBM_COLLISION_MRT;
     // MRT: s_k / |M_k|^2 of (e, eps, q_x, q_y, p_xx, p_xy), |M_k|^2 = 36, 36,
     // 12, 12, 4, 4 for the orthogonal moment basis of Eq. 4

@@ -253,10 +253,11 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu(KParams p,
         double mu = mux[node];
         if (!p.kappa_zero) mu -= p.kappa * dyy[k];
         mu_out[node] = mu;
-        bA[E.e[k]] = mu;
+        // wetting walls hold mu at mu_wall: mu - mu_wall, extended oddly
+        bA[E.e[k]] = p.wet ? mu - p.mu_wall : mu;
     }
     __syncthreads();
-    cfm_solve(p, m, E, bA, bB, 1.0, dym);
+    cfm_solve(p, m, E, bA, bB, p.wet ? -1.0 : 1.0, dym);
 #pragma unroll
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;

@@ -32,6 +32,9 @@ struct KParams {
     // 1 pseudopotential comparison model (Sec. 5.1)
     int mrt, sc;
     double mrt_w[6];
+    // wetting walls: mu is held at mu_wall (mesh units) on the walls
+    int wet;
+    double mu_wall;
     double cfd_a2, cfd_b4;  // a/2 and b/4 of Eq. 37 (h = 1)
     double pcr_c[kMaxStages], pcr_g[kMaxStages];
     // factorised inverse of the circulant compact-scheme matrix (fast path):

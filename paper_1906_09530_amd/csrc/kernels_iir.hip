@@ -361,7 +361,16 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
             mu_out[node] = v;
         }
     }
-    iir_solve<LC>(p, m, p.iir_qL_col, mu, 1.0, L, dym);
+    if (p.wet) {
+        // wetting walls hold mu at mu_wall: differentiate mu - mu_wall on its
+        // odd extension about the walls
+        double mw[LC];
+#pragma unroll
+        for (int k = 0; k < LC; ++k) mw[k] = mu[k] - p.mu_wall;
+        iir_solve<LC>(p, m, p.iir_qL_col, mw, -1.0, L, dym);
+    } else {
+        iir_solve<LC>(p, m, p.iir_qL_col, mu, 1.0, L, dym);
+    }
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k)

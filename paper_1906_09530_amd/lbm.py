@@ -31,6 +31,7 @@ class Params(C.Structure):
         ("mu_cap", C.c_double), ("cfd_alpha", C.c_double), ("wall_ux", C.c_double),
         ("collision", C.c_int32), ("force", C.c_int32),
         ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
+        ("wetting", C.c_int32), ("mu_wall", C.c_double),
     ]
 
 
@@ -42,13 +43,13 @@ MRT_RATES = (1.64, 1.54, 1.9)
 
 def params(eos, T_r, nx, ny, *, kappa, tau, k, mu_cap=math.inf, cfd_alpha=1.0 / 3.0, bc_y=0,
            wall_ux=0.0, omega=0.344, a=None, b=None, R=1.0, collision=COLLISION_BGK,
-           force=FORCE_CP, rates=MRT_RATES):
+           force=FORCE_CP, rates=MRT_RATES, wetting=0, mu_wall=0.0):
     da, db = EOS_AB[eos]
     return Params(nx=nx, ny=ny, bc_y=bc_y, eos=eos, a=da if a is None else a,
                   b=db if b is None else b, R=R, omega=omega, T_r=T_r, kappa=kappa, tau=tau,
                   k=k, mu_cap=mu_cap, cfd_alpha=cfd_alpha, wall_ux=wall_ux,
                   collision=collision, force=force, s_e=rates[0], s_eps=rates[1],
-                  s_q=rates[2])
+                  s_q=rates[2], wetting=wetting, mu_wall=mu_wall)
 
 
 class LBMError(RuntimeError):

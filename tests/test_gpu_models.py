@@ -208,3 +208,32 @@ def test_pseudopotential_rejects_densities_outside_the_domain():
     with pytest.raises(lbm.LBMError) as ei:
         lbm.Solver(p, rho)
     assert ei.value.status == lbm.LBM_E_DOMAIN
+
+
+# ---- wetting walls (prescribed wall chemical potential) -------------------
+
+@pytest.mark.parametrize("nx,ny,dmu", [(192, 96, -0.1), (192, 96, 0.1), (98, 66, -0.1)])
+def test_wetting_walls_match_oracle(nx, ny, dmu):
+    """A CS drop on the bottom wall between walls that hold the chemical
+    potential at mu_b + dmu (factorised-inverse column kernel at 192 x 96,
+    the general reduction kernel at 98 x 66)."""
+    import mpmath as mp
+    e = A.EOS(A.EOS_CS)
+    T, al = e.temperature(0.7)
+    g, l = A.coexistence(A.EOS_CS, 0.7)
+    mub = float(e.mu0(mp.mpf(g), T, al))
+    p, op = _pair(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.9, k=0.2, bc_y=1, wetting=1,
+                  mu_wall=mub + dmu)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, ny / 3, 4.0, center=(nx / 2, -0.5), seed=41,
+                                    noise=1e-6)
+    _run("wet%dx%d-dmu%+g" % (nx, ny, dmu), p, op, rho0, ux0, uy0, [100, 400])
+
+
+def test_wetting_is_rejected_where_it_does_not_apply():
+    rho = np.full((64, 64), 0.2)
+    for kw in (dict(bc_y=0, wetting=1), dict(bc_y=1, wetting=1, force=lbm.FORCE_SC),
+               dict(bc_y=1, wetting=2)):
+        p = lbm.params(lbm.EOS_CS, 0.7, 64, 64, kappa=0.1, tau=1.0, k=0.2, **kw)
+        with pytest.raises(lbm.LBMError) as ei:
+            lbm.Solver(p, rho)
+        assert ei.value.status == lbm.LBM_E_INVALID

@@ -406,3 +406,42 @@ def test_drop_spreading_law(Re, k, W, collision, rates):
         Re, min(C), max(C), expo, np.exp(logc)), flush=True)
     assert 1.2 <= min(C) and max(C) <= 1.55
     assert 0.5 <= expo <= 0.72
+
+
+def test_contact_angle_follows_the_wall_chemical_potential():
+    """Wetting walls (the chemical-potential boundary the paper takes from
+    its ref. [45]): a CS drop (T/Tc = 0.7, k = 0.2, 5-node interface) resting
+    on the bottom wall of a 192 x 96 box whose walls hold the chemical
+    potential at mu_b + dmu, mu_b the coexistence value.  The contact angle
+    (from the drop's base half-width a and height h on its axis,
+    theta = 2 atan(h / a) for a circular cap) is 90 degrees at dmu = 0 and
+    moves monotonically, and nearly linearly, with dmu: a lower wall
+    potential wets (the force -rho grad mu draws liquid toward it).
+    Measured after 300,000 steps: 68, 80, 91, 100, 110 degrees for
+    dmu = -0.2 ... 0.2 (3 million steps give the same angles to a degree)."""
+    T_r, k, nx, ny = 0.7, 0.2, 192, 96
+    e = A.EOS(A.EOS_CS)
+    T, al = e.temperature(T_r)
+    g, l = A.coexistence(A.EOS_CS, T_r)
+    mub = float(e.mu0(mp.mpf(g), T, al))
+    w1 = float(mp.re(e.interface(T_r)["width1"]))
+    kap = (5 * k / w1) ** 2
+    dmus = (-0.2, -0.1, 0.0, 0.1, 0.2)
+    ps = [lbm.params(lbm.EOS_CS, T_r, nx, ny, kappa=kap, tau=1.0, k=k, bc_y=1, wetting=1,
+                     mu_wall=mub + d) for d in dmus]
+    rho = inputs.droplet(nx, ny, g, l, 32.0, 5.0, center=(nx / 2, -0.5))[0]
+    b = lbm.Batch(ps, [rho] * len(ps))
+    b.step(300_000)
+    half = 0.5 * (g + l)
+    theta = []
+    print("\n dmu     base a  height h  contact angle")
+    for i, d in enumerate(dmus):
+        r = b.moments(i)[0]
+        assert np.isfinite(r).all()
+        a = (r[0] > half).sum() / 2.0
+        h = (r[:, nx // 2] > half).sum()
+        theta.append(2 * np.degrees(np.arctan(h / a)))
+        print(" %+.2f   %5.1f   %3d       %.1f" % (d, a, h, theta[-1]), flush=True)
+    assert all(t1 < t2 for t1, t2 in zip(theta, theta[1:]))
+    assert abs(theta[2] - 90.0) <= 3.0
+    assert theta[0] < 75.0 and theta[-1] > 105.0
