@@ -418,7 +418,7 @@ def test_split_collision_for_long_rows(nx, ny, walls):
     the oracle after 100 and 200 steps; a run resumed
     from its own state ends bitwise where the uninterrupted one does (the
     groups formed at the seams equal those of f); and the whole-row variant
-    agrees to round-off."""
+    agrees to round-off, also when a run switches to it after split steps."""
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls)
     g, l = A.coexistence(p.eos, p.T_r)
@@ -444,6 +444,13 @@ def test_split_collision_for_long_rows(nx, ny, walls):
     c.step(200)
     erc, evc = _errors(c.moments(), a.moments())
     assert erc <= 1e-12 and evc <= 1e-10
+    d = lbm.Solver(p, rho0, ux0, uy0)
+    d.set_collision_variant(2)
+    d.step(100)
+    d.set_collision_variant(0)
+    d.step(100)
+    erd, evd = _errors(d.moments(), a.moments())
+    assert erd <= 1e-12 and evd <= 1e-10
     with pytest.raises(lbm.LBMError):
         lbm.Solver(p, rho0, ux0, uy0).set_collision_variant(1)   # rows need 1024 threads
 
