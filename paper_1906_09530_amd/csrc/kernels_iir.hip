@@ -343,10 +343,19 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
         }
         return;
     }
-    double r[LC];
+    // With chunks of 8 or more nodes (one 1024-thread workgroup per CU at
+    // most) both inputs are loaded up front, so that their latencies
+    // overlap; 4-node chunks keep the registers for two workgroups per CU
+    // and load the row part of mu after the solves.
+    constexpr bool kEarly = LC >= 8;
+    double r[LC], mx[LC];
     if (m.ok) {
 #pragma unroll
         for (int k = 0; k < LC; ++k) r[k] = rho[(size_t)(j0 + k) * nx + col];
+        if (kEarly) {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) mx[k] = mux[(size_t)(j0 + k) * nx + col];
+        }
     }
     double dyr[LC], dyy[LC], mu[LC], dym[LC];
     iir_solve<LC>(p, m, p.iir_qL_col, r, 1.0, L, dyr);
@@ -355,7 +364,7 @@ __device__ __forceinline__ void cols_mu_body(const KParams &p, int x0,
 #pragma unroll
         for (int k = 0; k < LC; ++k) {
             const size_t node = (size_t)(j0 + k) * nx + col;
-            double v = mux[node];
+            double v = kEarly ? mx[k] : mux[node];
             if (!p.kappa_zero) v -= p.kappa * dyy[k];
             mu[k] = v;
             mu_out[node] = v;
@@ -1008,7 +1017,8 @@ hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const doubl
 hipError_t launch_group_seams(const KParams &p, const double *fout, double *gout, hipStream_t s)
 {
     const size_t seams = (size_t)p.ny * (p.nx / p.seg_len) * 2;
-    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 255) / 256)), dim3(256), 0, s, p,
+    // one wave per workgroup, so that the few seam nodes spread over every CU
+    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 63) / 64)), dim3(64), 0, s, p,
                        fout, gout);
     return hipGetLastError();
 }
