@@ -385,6 +385,38 @@ def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
             "dominant": names[dom], "dominant_ms": ms[dom]}
 
 
+def small_mesh_bench(torch, lbm, inputs, steps=2000):
+    """The 64 x 64 periodic CS drop (T/Tc = 0.7, kappa = 0, k = 1, fourth-order
+    compact scheme, tau = 1, R = 16, tanh width 4, 1e-6 noise) for its 2000
+    steps, its kernels launched one by one and replayed from captured HIP
+    graphs of 100 steps (same results bit for bit): on a mesh this small the
+    three kernels of a step take a few microseconds each and launch overhead
+    sets the rate."""
+    p = lbm.params(lbm.EOS_CS, 0.7, 64, 64, kappa=0.0, tau=1.0, k=1.0, cfd_alpha=0.25)
+    rho_g, rho_l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.droplet(64, 64, rho_g, rho_l, 16.0, 4.0, seed=1, noise=1e-6)
+    out = {"workload": "64x64 periodic CS drop, T/Tc=0.7, kappa=0, k=1, 4th-order CFM, tau=1, "
+                       "R=16, W=4", "steps": steps}
+    states = []
+    for name, G in (("eager", 0), ("graph100", 100)):
+        sv = lbm.Solver(p, rho0, ux0, uy0)
+        sv.set_graph_steps(G)
+        sv.step(200)
+        sv.synchronize()
+        best = math.inf
+        for _ in range(3):
+            t0 = time.perf_counter()
+            sv.step(steps)
+            sv.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        states.append(sv.get_state())
+        sv.close()
+        us = best / steps * 1e6
+        out[name] = {"us_per_step": round(us, 3), "MLUPS": round(64 * 64 / us, 1)}
+    out["graph_equals_eager_bitwise"] = bool((states[0] == states[1]).all())
+    return out
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -537,6 +569,8 @@ def main():
         splash = splash_hbm(torch, lbm, inputs, kernel_steps=args.kernel_steps)
         if args.splash == "full":
             splash["two_frames_10000_steps"] = splash_bench(torch, lbm, inputs)
+    print("64 x 64 drop: launches one by one and from graphs", file=sys.stderr, flush=True)
+    small = small_mesh_bench(torch, lbm, inputs)
     copy_big_gbs = copy_bandwidth(torch, 2 << 30, reps=5)
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
     warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)
@@ -597,6 +631,7 @@ def main():
         "wall_s": round(wall, 3),
         "drop_after_run": report,
         "splash_hbm": splash,
+        "small_mesh_64": small,
         "sweep": sweep,
         "warm_start": warm,
         "cpu_baseline": cpu,

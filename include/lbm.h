@@ -268,6 +268,20 @@ lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
 #define LBM_NOALLOC_MAX_NODES 262144
 lbm_status lbm_step_noalloc(const lbm_params *p, double *f, int64_t nsteps, void *hip_stream);
 
+/* Replay runs of steps from captured HIP graphs: lbm_step and
+ * lbm_run_until_converged then enqueue every whole run of `steps` time steps
+ * (rounded up to an even count, so that a run ends in the buffer it started
+ * from) as one graph launch, and the rest kernel by kernel.  The kernels,
+ * their order and the results are those of the launches one by one; on
+ * small meshes, whose kernels take a few microseconds, the launches
+ * themselves set the step time, and one graph launch replaces 3 x steps of
+ * them.  Two graphs (one per starting buffer) are captured on first use, on
+ * a stream the context creates, and captured again after the autotuner or
+ * the collision or column settings change the pass shapes.  0 (the
+ * default) launches every kernel separately.  LBM_E_INVALID for steps
+ * outside [0, 100000]. */
+lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int64_t steps);
+
 /* Steps taken since lbm_init. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 

@@ -34,6 +34,11 @@ struct lbm_ctx {
     int64_t steps = 0;
     lbm_status sticky = LBM_OK;
     std::string err;
+    // runs of graph_steps steps (even; 0: none) replay a captured graph, one
+    // per starting buffer, captured on the context's own capture stream
+    int64_t graph_steps = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -255,19 +260,74 @@ void carve(lbm_ctx *c, int red_blocks)
 // One step = pass A, pass B, pass C.  The first observation plane doubles as
 // the F_x scratch of the split collision pass: the observation planes are
 // only written by calls that run between steps on the same stream.
-lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
+lbm_status enqueue_steps_on(lbm_ctx *c, int64_t n, hipStream_t st)
 {
     for (int64_t s = 0; s < n; ++s) {
         const double *fc = c->f[c->cur];
         double *fn = c->f[1 - c->cur];
-        HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, c->stream));
-        HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream));
+        HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, st));
+        HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, st));
         HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->rho,
-                                      c->obs, c->stream));
+                                      c->obs, st));
         c->cur = 1 - c->cur;
         c->steps += 1;
     }
     return LBM_OK;
+}
+
+// Graphs hold the pass shapes they were captured with: drop them whenever
+// those change.
+void drop_graphs(lbm_ctx *c)
+{
+    for (hipGraphExec_t &g : c->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// graph_steps steps from the current buffer as one graph launch on the
+// context's stream (an even count, so the state returns to the same buffer).
+lbm_status enqueue_graph(lbm_ctx *c)
+{
+    hipGraphExec_t &ex = c->gexec[c->cur];
+    if (!ex) {
+        if (!c->cap) HIP_OR(c, hipStreamCreate(&c->cap));
+        const int cur0 = c->cur;
+        const int64_t steps0 = c->steps;
+        hipGraph_t g = nullptr;
+        HIP_OR(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        const lbm_status st = enqueue_steps_on(c, c->graph_steps, c->cap);
+        const hipError_t e = hipStreamEndCapture(c->cap, &g);
+        c->cur = cur0;
+        c->steps = steps0;
+        if (st != LBM_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != LBM_OK ? st
+                                : fail(c, LBM_E_DEVICE, std::string("graph capture failed: ") +
+                                                            hipGetErrorString(e));
+        }
+        const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            ex = nullptr;
+            return fail(c, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        }
+    }
+    HIP_OR(c, hipGraphLaunch(ex, c->stream));
+    c->steps += c->graph_steps;
+    return LBM_OK;
+}
+
+lbm_status enqueue_steps(lbm_ctx *c, int64_t n)
+{
+    const int64_t G = c->graph_steps;
+    if (G > 0) {
+        for (; n >= G; n -= G) {
+            const lbm_status st = enqueue_graph(c);
+            if (st != LBM_OK) return st;
+        }
+    }
+    return enqueue_steps_on(c, n, c->stream);
 }
 
 // rho, mu and F_y of the current state into the context's field buffers.
@@ -782,6 +842,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     if (err != hipSuccess)
         return fail(c, LBM_E_DEVICE, std::string("autotune failed: ") + hipGetErrorString(err));
     (void)collision_variant(&c->kp, best_variant);
+    drop_graphs(c);
     if (count) *count = n;
     return LBM_OK;
 }
@@ -794,6 +855,7 @@ lbm_status lbm_set_collision_variant(lbm_ctx *c, int variant)
     if (!collision_variant(&kp, variant))
         return fail(c, LBM_E_INVALID, "collision variant not available for this mesh");
     c->kp = kp;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -811,6 +873,18 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
     else if (!kp.use_iir_cols)
         return fail(c, LBM_E_INVALID, "this column length cannot use the factorised solve");
     c->kp = kp;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_graph_steps(lbm_ctx *c, int64_t steps)
+{
+    lbm_status st = enter(c);
+    if (st != LBM_OK) return st;
+    if (steps < 0 || steps > 100000) return fail(c, LBM_E_INVALID, "steps must be in [0, 100000]");
+    const int64_t G = steps + (steps & 1);
+    if (G != c->graph_steps) drop_graphs(c);
+    c->graph_steps = G;
     return LBM_OK;
 }
 
@@ -827,11 +901,11 @@ lbm_status lbm_synchronize(lbm_ctx *c)
 void lbm_destroy(lbm_ctx *c)
 {
     if (!c) return;
-    if (c->owns_mem && c->mem) {
-        (void)hipSetDevice(c->device);
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->mem);
-    }
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    if (c->owns_mem && c->mem) (void)hipFree(c->mem);
     delete c;
 }
 

@@ -89,6 +89,7 @@ def load():
         "lbm_get_state": (i32, [P, P, i32]),
         "lbm_set_state": (i32, [P, P, i32]),
         "lbm_time_passes": (i32, [P, i64, pd]),
+        "lbm_set_graph_steps": (i32, [P, i64]),
         "lbm_time_step_kernels": (i32, [P, i64, pd, C.POINTER(C.c_int)]),
         "lbm_eos_values": (i32, [pp, d, pd, pd]),
         "lbm_autotune": (i32, [P, i32, C.POINTER(C.c_int), C.POINTER(C.c_int), pd,
@@ -267,6 +268,12 @@ class Solver:
         out = (C.c_double * 3)()
         _check(load().lbm_time_passes(self.ctx, int(n), out), self.ctx)
         return list(out)
+
+    def set_graph_steps(self, n):
+        """Replay whole runs of n steps (rounded up to even) from captured
+        HIP graphs in step() and run_until_converged(); 0 launches kernel by
+        kernel."""
+        _check(load().lbm_set_graph_steps(self.ctx, int(n)), self.ctx)
 
     def time_step_kernels(self, n):
         """Average ms of each kernel over n real steps (events around every

@@ -515,3 +515,55 @@ def test_full_size_1000_steps(name, golden_dir):
                    np.abs(vy.ravel()[idx] - gold["vy"]).max()) / float(gold["vmax"]))
     print("  %d nodes: rel err rho %.2e, v %.2e" % (len(idx), er, ev), flush=True)
     assert er <= TOL and ev <= TOL
+
+
+@pytest.mark.parametrize("case", ["cs64", "pr300x200walls", "split3072x40"])
+def test_graph_replay_matches_launches(case):
+    """Runs of steps replayed from captured HIP graphs (lbm_set_graph_steps)
+    give the state of the same steps launched kernel by kernel, bit for bit:
+    with eager work between the replays (moments, state reads, a remainder
+    shorter than a graph), after the pass shapes change (the graphs are
+    captured again), and inside run_until_converged."""
+    if case == "cs64":
+        p = lbm.params(lbm.EOS_CS, 0.7, 64, 64, kappa=0.0, tau=1.0, k=1.0, cfd_alpha=0.25)
+        g, l = lbm.maxwell(p)
+        init = inputs.droplet(64, 64, g, l, 16.0, 4.0, seed=1, noise=1e-6)
+    elif case == "pr300x200walls":
+        p = lbm.params(lbm.EOS_PR, 0.6, 300, 200, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0,
+                       bc_y=1, wall_ux=0.01)
+        g, l = lbm.maxwell(p)
+        init = inputs.droplet(300, 200, g, l, 50.0, 5.0, seed=7, noise=1e-6,
+                              center=(140.0, 95.0))
+    else:
+        p = lbm.params(lbm.EOS_CS, 0.7, 3072, 40, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                       bc_y=1)
+        g, l = lbm.maxwell(p)
+        init = inputs.droplet(3072, 40, g, l, 10.0, 3.0, seed=23, noise=1e-4,
+                              center=(1023.5, 20.0))
+    print("\n[case] graph replay %s" % case, flush=True)
+    a = lbm.Solver(p, *init)
+    b = lbm.Solver(p, *init)
+    b.set_graph_steps(9)            # rounded up to 10
+    for n in (35, 20, 7):
+        a.step(n)
+        b.step(n)
+        np.testing.assert_array_equal(b.get_state(), a.get_state())
+        for x, y in zip(b.moments(), a.moments()):
+            np.testing.assert_array_equal(x, y)
+    # new pass shapes: the graphs are captured again
+    if case == "split3072x40":
+        a.set_collision_variant(2)
+        b.set_collision_variant(2)
+    else:
+        a.set_column_shape(1, 0)
+        b.set_column_shape(1, 0)
+    a.step(40)
+    b.step(40)
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    ra = a.run_until_converged(0.0, check_every=20, max_steps=60)
+    rb = b.run_until_converged(0.0, check_every=20, max_steps=60)
+    assert ra[1] == rb[1] == 60 and ra[2] == rb[2]
+    np.testing.assert_array_equal(b.get_state(), a.get_state())
+    assert a.steps_taken == b.steps_taken == 162
+    a.close()
+    b.close()
