@@ -40,15 +40,17 @@ HBM_PEAK_GBS = 8000.0
 #     and the row part of mu (2 x 8)
 #   column pass B: read rho and the row part of mu; write mu, F_y
 #   row pass C: read f (9 x 8), mu, F_y; write f (9 x 8) and its three
-#     density groups (3 x 8)
+#     density groups (3 x 8); over row segments (long rows) it also reads
+#     rho (8), and the window's 52 nodes past each end of a 512-node segment
+#     add ~3 B of rho and mu reads
 # and, for the roofline, the algorithmic count of the collide-and-stream
 # kernel: read f and the two force or chemical-potential inputs, write f
 # (72 + 24 + 72 = 168 B per lattice update); the floor of any scheme is f
 # read and written once (144 B per update).
 PASS_NAMES = ["rows_rho", "cols_mu", "rows_collide"]
 PASS_BYTES = [40, 32, 184]
-SPLIT_NAMES = ["rows_rho", "cols_mu", "rows_fx", "collide_seg", "group_seams"]
-SPLIT_BYTES = [40, 32, 24, 184, 0]
+SEG_NAMES = ["rows_rho", "cols_mu", "collide_seg"]
+SEG_BYTES = [40, 32, 192]
 COLLIDE_ALG_BYTES = 168
 FLOOR_BYTES = 144
 
@@ -356,7 +358,9 @@ def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
     d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
     s = lbm.Solver(p, *d, stream=stream.cuda_stream)
     s.step(20)
-    s.autotune(5)
+    tune = s.autotune(5)
+    # the collision variant the autotuner kept (2: over row segments)
+    variant = min((k for k in tune if k[0] == 0), key=tune.get)[1]
     s.step(20)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -369,13 +373,13 @@ def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
     r = s.moments()[0]
     finite = bool(np.isfinite(r).all())
     s.close()
-    names = SPLIT_NAMES if len(ms) == 5 else PASS_NAMES
-    nbytes = SPLIT_BYTES if len(ms) == 5 else PASS_BYTES
+    names = SEG_NAMES if variant == 2 else PASS_NAMES
+    nbytes = SEG_BYTES if variant == 2 else PASS_BYTES
     N = nx * ny
     dom = int(np.argmax(ms))
     return {"workload": "drop splashing on a 40-node film between walls, CS, 4096x2048, "
                         "T/Tc=0.6, R=100, tau=0.6, k=0.2, kappa=0.1",
-            "nx": nx, "ny": ny, "finite": finite, "steps": steps,
+            "nx": nx, "ny": ny, "finite": finite, "steps": steps, "collision_variant": variant,
             "ms_per_step": round(ms_step, 6), "MLUPS": round(N / (ms_step * 1e-3) / 1e6, 1),
             "floor_equivalent_GB_s": round(FLOOR_BYTES * N / (ms_step * 1e-3) / 1e9, 1),
             "kernels": {names[i]: {"avg_ms": round(ms[i], 6),

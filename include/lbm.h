@@ -73,7 +73,9 @@ typedef enum {
 } lbm_eos;
 
 typedef struct {
-    int32_t nx, ny;     /* mesh nodes; 8 <= nx, ny <= 4096 */
+    int32_t nx, ny;     /* mesh nodes; 8 <= nx, ny <= 4096, or longer lines:
+                           nx up to 2^20 as a multiple of 4, ny up to 8192 as a
+                           multiple of 8 or up to 16384 as a multiple of 16 */
     int32_t bc_y;       /* 0: periodic in y; 1: bounce-back walls in y */
     int32_t eos;        /* lbm_eos */
     double a, b, R;     /* EOS constants in momentum space (Sec. 3.2) */
@@ -195,9 +197,8 @@ lbm_status lbm_time_passes(lbm_ctx *ctx, int64_t nsteps, double *ms_per_pass);
  * with a HIP event recorded on the context's stream before and after every
  * kernel, so each kernel is timed inside the real step sequence.  ms[k]
  * receives the average milliseconds of kernel k and *count the number of
- * kernels per step: 3 (row pass A, column pass B, collision pass C) or, with
- * the split collision variant, 5 (A, B, F_x over rows, collision over row
- * segments, density groups at the segment seams).  ms needs room for 5.
+ * kernels per step: 3 (row pass A, column pass B, collision pass C in the
+ * selected variant).  ms needs room for 3.
  * Synchronises the stream. */
 lbm_status lbm_time_step_kernels(lbm_ctx *ctx, int64_t nsteps, double *ms, int *count);
 
@@ -231,13 +232,16 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, dou
  *   0  one kernel over whole rows, reading the populations twice;
  *   1  one kernel over whole rows holding the populations in registers
  *      (rows of at most 1024 nodes; the default there);
- *   2  split for long rows (more than 1024 nodes, dividing into equal
- *      segments of at most 1024 nodes in 4-node chunks): F_x over whole rows
- *      from the density and mu planes, then the collision over the row
- *      segments holding the populations in registers.
- *      F_x then takes rho from pass A (the sum of the density groups)
- *      instead of the collision's own sum of f, so results differ from
- *      variants 0 and 1 in the last bits.
+ *   2  over row segments of 512 nodes (rows longer than 512 nodes, a
+ *      multiple of 4; the last segment may be shorter): one workgroup per
+ *      segment holds its populations in registers and takes F_x from the
+ *      density and mu planes over a window of 52 nodes past each end of the
+ *      segment, with the same values as whole-row derivatives of those
+ *      planes.  F_x then takes rho from pass A (the sum of the density
+ *      groups) instead of the collision's own sum of f, so results differ
+ *      from variants 0 and 1 in the last bits.  Rows longer than 4096 nodes
+ *      take this variant only, and their pass A and observations run over
+ *      segments as well.
  * LBM_E_INVALID if the variant is not available for this mesh. */
 lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
 

@@ -46,6 +46,10 @@ namespace {
 thread_local std::string g_init_error;
 
 constexpr int kMaxLine = kMaxBlockElems;  // longest line a block holds in LDS
+// longer lines: rows over windowed segments (a whole number of 4-node
+// chunks), columns on the factorised solve with 8- or 16-node chunks
+constexpr int kMaxRow = 1 << 20;
+constexpr int kMaxCol = 16384;
 constexpr int kDefaultStripWidth = 4;     // columns per block before tuning
 constexpr int kDefaultChunk = 4;          // column nodes per thread before tuning
 
@@ -95,8 +99,13 @@ lbm_status validate(const lbm_params *p, std::string *why)
         return LBM_E_INVALID;
     };
     if (!p) return bad("params is NULL");
-    if (p->nx < 8 || p->ny < 8 || p->nx > kMaxLine || p->ny > kMaxLine)
-        return bad("nx and ny must lie in [8, 4096]");
+    if (p->nx < 8 || p->ny < 8 || p->nx > kMaxRow || p->ny > kMaxCol)
+        return bad("nx must lie in [8, 1048576] and ny in [8, 16384]");
+    if (p->nx > kMaxLine && p->nx % kIirRowChunk != 0)
+        return bad("rows longer than 4096 nodes must be a multiple of 4");
+    if (p->ny > kMaxLine && !(p->ny % 16 == 0 || (p->ny <= 8192 && p->ny % 8 == 0)))
+        return bad("columns longer than 4096 nodes must be a multiple of 8 (up to 8192) "
+                   "or of 16");
     if (p->bc_y != 0 && p->bc_y != 1) return bad("bc_y must be 0 or 1");
     if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS) return bad("unknown EOS");
     if (!(finite(p->a) && p->a > 0 && finite(p->b) && p->b > 0 && finite(p->R) && p->R > 0))
@@ -203,6 +212,14 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     set_row_shape(&k);
     k.row_keep = 1;
     set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
+    // columns longer than one workgroup's reduction holds: the factorised
+    // solve with the shortest chunk that fits
+    for (int lc : {8, 16})
+        if (!k.use_iir_cols && k.ny > kMaxLine) set_col_shape(&k, 1, lc);
+    if (!k.use_iir_cols && k.ny > kMaxLine) {
+        *why = "no column solve holds columns of this length";
+        return false;
+    }
     *kp = k;
     return true;
 }
@@ -257,9 +274,7 @@ void carve(lbm_ctx *c, int red_blocks)
     c->red = (double *)m;
 }
 
-// One step = pass A, pass B, pass C.  The first observation plane doubles as
-// the F_x scratch of the split collision pass: the observation planes are
-// only written by calls that run between steps on the same stream.
+// One step = pass A, pass B, pass C.
 lbm_status enqueue_steps_on(lbm_ctx *c, int64_t n, hipStream_t st)
 {
     for (int64_t s = 0; s < n; ++s) {
@@ -267,8 +282,7 @@ lbm_status enqueue_steps_on(lbm_ctx *c, int64_t n, hipStream_t st)
         double *fn = c->f[1 - c->cur];
         HIP_OR(c, launch_rows_rho(c->kp, fc, c->g[c->cur], c->rho, c->mux, st));
         HIP_OR(c, launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, st));
-        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->rho,
-                                      c->obs, st));
+        HIP_OR(c, launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, c->g[1 - c->cur], c->rho, st));
         c->cur = 1 - c->cur;
         c->steps += 1;
     }
@@ -349,12 +363,14 @@ lbm_status copy_out(lbm_ctx *c, double *dst, const double *src, size_t n, int on
 }
 
 // Collision pass variant (fast rows only): 0 one pass reading f twice,
-// 1 one pass holding f in registers (rows of up to 1024 nodes), 2 split into
-// F_x over whole rows and the collision over row segments holding f in
-// registers (rows of at least 2048 nodes in whole 1024-node segments).
+// 1 one pass holding f in registers (rows of up to 1024 nodes), 2 one pass
+// over row segments holding f in registers, F_x from a window around each
+// segment (rows longer than one segment; the only variant for rows longer
+// than one workgroup holds).
 bool collision_variant(KParams *kp, int variant)
 {
     const bool rows256 = kp->rows_per_block * (kp->nx / kIirRowChunk) <= 256;
+    if (kp->row_win && variant != 2) return false;
     switch (variant) {
     case 0: kp->row_keep = 0; kp->row_split = 0; return true;
     case 1:
@@ -556,8 +572,8 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *vx, double *vy, int dst_
     if (st != LBM_OK) return st;
     if ((st = enqueue_fields(c)) != LBM_OK) return st;
     const size_t N = c->N;
-    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, c->obs, c->obs + N,
-                                  c->obs + 2 * N, nullptr, c->stream));
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, c->rho, c->obs,
+                                  c->obs + N, c->obs + 2 * N, nullptr, c->stream));
     if ((st = copy_out(c, rho, c->obs, N, dst_on_device)) != LBM_OK) return st;
     if ((st = copy_out(c, vx, c->obs + N, N, dst_on_device)) != LBM_OK) return st;
     if ((st = copy_out(c, vy, c->obs + 2 * N, N, dst_on_device)) != LBM_OK) return st;
@@ -571,8 +587,8 @@ lbm_status lbm_force_fields(lbm_ctx *c, double *mu, double *Fx, double *Fy, int 
     if (st != LBM_OK) return st;
     if ((st = enqueue_fields(c)) != LBM_OK) return st;
     const size_t N = c->N;
-    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, nullptr, nullptr, nullptr,
-                                  c->obs, c->stream));
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, c->rho, nullptr, nullptr,
+                                  nullptr, c->obs, c->stream));
     if ((st = copy_out(c, mu, c->mu, N, dst_on_device)) != LBM_OK) return st;
     if ((st = copy_out(c, Fx, c->obs, N, dst_on_device)) != LBM_OK) return st;
     if ((st = copy_out(c, Fy, c->fy, N, dst_on_device)) != LBM_OK) return st;
@@ -652,8 +668,8 @@ lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int 
     double *fx = c->obs, *ux = c->obs + N, *uy = c->obs + 2 * N;
     const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if ((st = enqueue_fields(c)) != LBM_OK) return st;
-    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, nullptr, nullptr, nullptr,
-                                  fx, c->stream));
+    HIP_OR(c, launch_rows_observe(c->kp, c->f[c->cur], c->mu, c->fy, c->rho, nullptr, nullptr,
+                                  nullptr, fx, c->stream));
     if (vx)
         HIP_OR(c, hipMemcpyAsync(ux, vx, N * sizeof(double), kind, c->stream));
     else
@@ -692,8 +708,7 @@ lbm_status lbm_time_passes(lbm_ctx *c, int64_t nsteps, double *ms_per_pass)
             if (q == 0) err = launch_rows_rho(c->kp, fc, gc, c->rho, c->mux, c->stream);
             if (q == 1) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
             if (q == 2)
-                err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs,
-                                          c->stream);
+                err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->stream);
         }
         if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -714,8 +729,7 @@ lbm_status lbm_time_step_kernels(lbm_ctx *c, int64_t nsteps, double *ms, int *co
     if (st != LBM_OK) return st;
     if (nsteps <= 0 || !ms || !count)
         return fail(c, LBM_E_INVALID, "nsteps > 0 and outputs required");
-    const bool split = c->kp.use_iir_rows && c->kp.row_split;
-    const int K = split ? 5 : 3;
+    const int K = 3;
     std::vector<hipEvent_t> ev((size_t)nsteps * (K + 1), nullptr);
     hipError_t err = hipSuccess;
     for (size_t i = 0; i < ev.size() && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
@@ -728,20 +742,9 @@ lbm_status lbm_time_step_kernels(lbm_ctx *c, int64_t nsteps, double *ms, int *co
         if (err == hipSuccess) err = hipEventRecord(e[1], c->stream);
         if (err == hipSuccess) err = launch_cols_mu(c->kp, c->rho, c->mux, c->mu, c->fy, c->stream);
         if (err == hipSuccess) err = hipEventRecord(e[2], c->stream);
-        if (split) {
-            if (err == hipSuccess) err = launch_rows_fx_iir(c->kp, c->rho, c->mu, c->obs, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
-            if (err == hipSuccess)
-                err = launch_collide_seg_iir(c->kp, fc, c->fy, c->obs, fn, gn, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[4], c->stream);
-            if (err == hipSuccess) err = launch_group_seams(c->kp, fn, gn, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[5], c->stream);
-        } else {
-            if (err == hipSuccess)
-                err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs,
-                                          c->stream);
-            if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
-        }
+        if (err == hipSuccess)
+            err = launch_rows_collide(c->kp, fc, c->mu, c->fy, fn, gn, c->rho, c->stream);
+        if (err == hipSuccess) err = hipEventRecord(e[3], c->stream);
         c->cur = 1 - c->cur;
         c->steps += 1;
     }
@@ -785,7 +788,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
             if (e == hipSuccess) e = launch_rows_rho(kp, fc, gc, c->rho, c->mux, c->stream);
             if (e == hipSuccess) e = launch_cols_mu(kp, c->rho, c->mux, c->mu, c->fy, c->stream);
             if (e == hipSuccess)
-                e = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->obs, c->stream);
+                e = launch_rows_collide(kp, fc, c->mu, c->fy, fn, gn, c->rho, c->stream);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -804,6 +807,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
         KParams kp = c->kp;
         set_col_shape(&kp, w, ch);
         if (kp.cols_per_block != w) continue;  // does not fit one block
+        if (!kp.use_iir_cols && kp.ny > kMaxLine) continue;
         // the general kernel ignores the chunk length: time it once
         if (!kp.use_iir_cols && ch != cand_c[0]) continue;
         double avg = 0.0;
@@ -868,6 +872,8 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
     KParams kp = c->kp;
     set_col_shape(&kp, width, chunk == 0 ? 4 : chunk);
     if (kp.cols_per_block != width) return fail(c, LBM_E_INVALID, "width does not fit a workgroup");
+    if (!kp.use_iir_cols && kp.ny > kMaxLine)
+        return fail(c, LBM_E_INVALID, "columns this long need the factorised solve");
     if (chunk == 0)
         kp.use_iir_cols = 0;
     else if (!kp.use_iir_cols)
@@ -1387,7 +1393,8 @@ lbm_status lbm_batch_moments(lbm_batch *b, int32_t sim, double *rho, double *vx,
     hipError_t e = launch_rows_rho(k, fc, gc, q.rho, q.mux, b->stream);
     if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
-        e = launch_rows_observe(k, fc, q.mu, q.fy, obs, obs + N, obs + 2 * N, nullptr, b->stream);
+        e = launch_rows_observe(k, fc, q.mu, q.fy, q.rho, obs, obs + N, obs + 2 * N, nullptr,
+                                b->stream);
     double *outs[3] = {rho, vx, vy};
     for (int i = 0; i < 3 && e == hipSuccess; ++i)
         if (outs[i])
@@ -1427,7 +1434,7 @@ lbm_status lbm_batch_set_velocity(lbm_batch *b, int32_t sim, const double *vx, c
     hipError_t e = launch_rows_rho(k, fc, gc, q.rho, q.mux, b->stream);
     if (e == hipSuccess) e = launch_cols_mu(k, q.rho, q.mux, q.mu, q.fy, b->stream);
     if (e == hipSuccess)
-        e = launch_rows_observe(k, fc, q.mu, q.fy, nullptr, nullptr, nullptr, fx, b->stream);
+        e = launch_rows_observe(k, fc, q.mu, q.fy, q.rho, nullptr, nullptr, nullptr, fx, b->stream);
     if (e == hipSuccess)
         e = vx ? hipMemcpyAsync(ux, vx, N * sizeof(double), hipMemcpyHostToDevice, b->stream)
                : hipMemsetAsync(ux, 0, N * sizeof(double), b->stream);

@@ -477,11 +477,11 @@ void set_row_shape(KParams *p)
     p->rows_per_block = R;
     p->row_threads = round_threads(R * p->nx);
     p->use_iir_rows = iir_rows_ok(*p);
-    // split collision pass: the fewest equal segments of at most kSegLen
-    // nodes, each a whole number of 4-node chunks (0: not available)
-    const int nseg = (p->nx + kSegLen - 1) / kSegLen;
-    p->seg_len = (p->nx % nseg == 0 && (p->nx / nseg) % kIirRowChunk == 0) ? p->nx / nseg : 0;
-    p->row_split = 0;
+    // row segments (the segment kernels): kSegLen nodes, the last one ragged;
+    // rows longer than one workgroup holds run every row pass over them
+    p->seg_len = kSegLen;
+    p->row_win = p->nx > kMaxWholeRow;
+    p->row_split = p->row_win;
 }
 
 void set_col_shape(KParams *p, int width, int chunk)
@@ -532,6 +532,7 @@ static bool col_fast(const KParams &p) { return p.ny >= kFastMinLine; }
 hipError_t launch_rows_rho(const KParams &p, const double *f, const double *g, double *rho,
                            double *mux, hipStream_t s)
 {
+    if (p.row_win) return launch_rows_rho_seg_iir(p, g, rho, mux, s);
     if (p.use_iir_rows) return launch_rows_rho_iir(p, g, rho, mux, s);
 #define GRID dim3(row_blocks(p)), dim3(p.row_threads), row_lds(p), s, p, f, rho, mux
     CPLBM_DISPATCH(k_rows_rho, row_fast(p), p.row_threads);
@@ -551,10 +552,9 @@ hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux
 
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
                                const double *fy, double *fout, double *gout, const double *rho,
-                               double *fx, hipStream_t s)
+                               hipStream_t s)
 {
-    if (p.use_iir_rows && p.row_split)
-        return launch_collide_split_iir(p, f, rho, mu, fy, fx, fout, gout, s);
+    if (p.row_split) return launch_collide_split_iir(p, f, rho, mu, fy, fout, gout, s);
     if (p.use_iir_rows)
         return launch_rows_collide_iir(p, f, mu, fy, fout, gout, nullptr, nullptr, nullptr,
                                        nullptr, false, s);
@@ -567,9 +567,10 @@ hipError_t launch_rows_collide(const KParams &p, const double *f, const double *
 }
 
 hipError_t launch_rows_observe(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *rho, double *vx, double *vy,
-                               double *fx, hipStream_t s)
+                               const double *fy, const double *rho_in, double *rho, double *vx,
+                               double *vy, double *fx, hipStream_t s)
 {
+    if (p.row_win) return launch_observe_seg_iir(p, f, rho_in, mu, fy, rho, vx, vy, fx, s);
     if (p.use_iir_rows)
         return launch_rows_collide_iir(p, f, mu, fy, nullptr, nullptr, rho, vx, vy, fx, true, s);
 #define GRID                                                                                 \

@@ -9,9 +9,10 @@ constexpr int kMaxStages = 8;        // parallel cyclic reduction stages
 constexpr int kElemsPerThread = 4;   // line elements held by one thread
 constexpr int kMaxBlockThreads = 1024;
 constexpr int kMaxBlockElems = kMaxBlockThreads * kElemsPerThread;  // 4096 doubles per LDS buffer
-// nodes of a column strip the factorised solve holds (one thread per chunk;
-// its LDS, four edge values and two carries per chunk, stays under ~50 KB)
-constexpr int kMaxColElems = 8192;
+// nodes of a column strip the factorised solve holds (one thread per chunk,
+// at most 1024 chunks; its LDS, four edge values and two carries per chunk,
+// stays under ~50 KB)
+constexpr int kMaxColElems = 16384;
 constexpr int kFastMinLine = 64;     // lines this long skip the general modulo indexing
 
 // Everything a kernel needs, passed by value.
@@ -42,15 +43,17 @@ struct KParams {
     // chunk length, its power q^LC and the number of carried chunks M
     int use_iir_rows, use_iir_cols, col_lc;
     int row_keep;   // collision pass holds f in registers (tuned)
-    int row_split;  // collision pass split for long rows (tuned; see below)
-    int seg_len;    // row segment of the split collision pass (0: none)
+    int row_split;  // collision pass over row segments (tuned; see below)
+    int row_win;    // rows beyond one workgroup: every row pass over segments
+    int seg_len;    // row segment of the segment kernels (0: none)
     int iir_m_row, iir_m_col;
     double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
     double iir_qp[17];
 };
 
 constexpr int kIirRowChunk = 4;
-constexpr int kSegLen = 1024;  // longest segment of the split collision pass
+constexpr int kSegLen = 512;          // row segment of the segment kernels
+constexpr int kMaxWholeRow = 4096;    // longest row one workgroup holds
 
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
@@ -71,15 +74,15 @@ hipError_t launch_cols_mu(const KParams &p, const double *rho, const double *mux
                           double *fy, hipStream_t s);
 // Pass C over rows: d/dx rho, d/dx mu, F_x, collision and streaming f -> fout,
 // and (fast kernels) the density groups gout of fout.  rho: pass A's density
-// plane and fx: N doubles of scratch, both used by the split variant
-// (row_split) only.
+// plane, read by the segment variant (row_split) only.
 hipError_t launch_rows_collide(const KParams &p, const double *f, const double *mu,
                                const double *fy, double *fout, double *gout, const double *rho,
-                               double *fx, hipStream_t s);
-// Pass C in observation mode: rho, v = u + F/(2 rho), F_x (any output may be null).
+                               hipStream_t s);
+// Pass C in observation mode: rho, v = u + F/(2 rho), F_x (any output may be
+// null).  rho_in: pass A's density plane, read over segments (row_win) only.
 hipError_t launch_rows_observe(const KParams &p, const double *f, const double *mu,
-                               const double *fy, double *rho, double *vx, double *vy,
-                               double *fx, hipStream_t s);
+                               const double *fy, const double *rho_in, double *rho, double *vx,
+                               double *vy, double *fx, hipStream_t s);
 // g = the density groups of f.
 hipError_t launch_density_groups(const KParams &p, const double *f, double *g, hipStream_t s);
 // f = feq(rho0, u0) (u0 pointers may be null: rest).
@@ -140,20 +143,19 @@ hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const doub
                                    const double *fy, double *fout, double *gout, double *o_rho,
                                    double *o_vx, double *o_vy, double *o_fx, bool observe,
                                    hipStream_t s);
-// Split collision pass for rows longer than kSegLen nodes that divide into
-// equal segments (seg_len) of at most kSegLen nodes in 4-node chunks: F_x
-// over whole rows into fx (N doubles of scratch, from the rho and mu planes),
-// then the collision over row segments into (fout, gout).
+// Row segments of kSegLen nodes (the last one ragged) for rows longer than
+// kSegLen whose length is a whole number of 4-node chunks: one workgroup per
+// segment, with the row derivatives taken over a window around it.  The
+// collision pass (f in registers into fout, gout; F_x from the rho plane of
+// pass A and the mu plane), pass A, and the observation pass.
 bool iir_split_ok(const KParams &p);
 hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
-                                    const double *mu, const double *fy, double *fx,
-                                    double *fout, double *gout, hipStream_t s);
-// The three kernels of the split pass, one launch each (the timing path
-// brackets each with events).
-hipError_t launch_rows_fx_iir(const KParams &p, const double *rho, const double *mu, double *fx,
-                              hipStream_t s);
-hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const double *fy,
-                                  const double *fx, double *fout, double *gout, hipStream_t s);
-hipError_t launch_group_seams(const KParams &p, const double *fout, double *gout, hipStream_t s);
+                                    const double *mu, const double *fy, double *fout,
+                                    double *gout, hipStream_t s);
+hipError_t launch_rows_rho_seg_iir(const KParams &p, const double *g, double *rho, double *mux,
+                                   hipStream_t s);
+hipError_t launch_observe_seg_iir(const KParams &p, const double *f, const double *rho,
+                                  const double *mu, const double *fy, double *o_rho, double *o_vx,
+                                  double *o_vy, double *o_fx, hipStream_t s);
 
 }  // namespace cplbm

@@ -92,6 +92,44 @@ __device__ __forceinline__ LineLds carve_lds(double *smem, const Chunk<LC> &m)
     return L;
 }
 
+// A chunk's part of a solve: the right-hand side of Eq. 37 from its values u
+// and the two values on each side, both recurrences from zero over the
+// chunk, and the two carries it publishes.
+template <int LC>
+__device__ __forceinline__ void iir_chunk(const KParams &p, const double (&u)[LC], double um2,
+                                          double um1, double up0, double up1, double (&y)[LC],
+                                          double (&z)[LC], double &Pc, double &Bc)
+{
+    const double q = p.iir_q;
+    double r[LC];
+    auto U = [&](int i) -> double {
+        return i == -2 ? um2 : i == -1 ? um1 : i == LC ? up0 : i == LC + 1 ? up1 : u[i];
+    };
+#pragma unroll
+    for (int k = 0; k < LC; ++k)
+        r[k] = p.cfd_a2 * (U(k + 1) - U(k - 1)) + p.cfd_b4 * (U(k + 2) - U(k - 2));
+    y[0] = r[0];
+#pragma unroll
+    for (int k = 1; k < LC; ++k) y[k] = r[k] + q * y[k - 1];
+    z[LC - 1] = 0.0;
+#pragma unroll
+    for (int k = LC - 2; k >= 0; --k) z[k] = q * (r[k + 1] + z[k + 1]);
+    Pc = y[LC - 1];
+    Bc = q * (r[0] + z[0]);
+}
+
+// The derivative on a chunk: its own recurrences plus the sums Yc and Zc
+// carried in from the chunks before and after it.
+template <int LC>
+__device__ __forceinline__ void iir_combine(const KParams &p, double Yc, double Zc,
+                                            const double (&y)[LC], const double (&z)[LC],
+                                            double (&d)[LC])
+{
+#pragma unroll
+    for (int k = 0; k < LC; ++k)
+        d[k] = p.iir_K * ((y[k] + p.iir_qp[k + 1] * Yc) + (z[k] + p.iir_qp[LC - 1 - k] * Zc));
+}
+
 // First derivative of u (parity par_u) along the thread's line; the whole
 // block calls it together.
 template <int LC>
@@ -130,26 +168,13 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
     }
     __syncthreads();
     const double q = p.iir_q;
-    double r[LC], y[LC], z[LC];
+    double y[LC], z[LC];
     if (m.ok) {
         // u at j0-2, j0-1 (end of the previous chunk), j0+LC, j0+LC+1 (start
         // of the next)
-        const double um2 = vbuf[m.eslot(c - 1, 2)], um1 = vbuf[m.eslot(c - 1, 3)];
-        const double up0 = vbuf[m.eslot(c + 1, 0)], up1 = vbuf[m.eslot(c + 1, 1)];
-        auto U = [&](int i) -> double {
-            return i == -2 ? um2 : i == -1 ? um1 : i == LC ? up0 : i == LC + 1 ? up1 : u[i];
-        };
-#pragma unroll
-        for (int k = 0; k < LC; ++k)
-            r[k] = p.cfd_a2 * (U(k + 1) - U(k - 1)) + p.cfd_b4 * (U(k + 2) - U(k - 2));
-        y[0] = r[0];
-#pragma unroll
-        for (int k = 1; k < LC; ++k) y[k] = r[k] + q * y[k - 1];
-        z[LC - 1] = 0.0;
-#pragma unroll
-        for (int k = LC - 2; k >= 0; --k) z[k] = q * (r[k + 1] + z[k + 1]);
-        const double Pc = y[LC - 1];
-        const double Bc = q * (r[0] + z[0]);
+        double Pc, Bc;
+        iir_chunk<LC>(p, u, vbuf[m.eslot(c - 1, 2)], vbuf[m.eslot(c - 1, 3)],
+                      vbuf[m.eslot(c + 1, 0)], vbuf[m.eslot(c + 1, 1)], y, z, Pc, Bc);
         cP[m.pslot(m.c)] = Pc;
         cB[m.bslot(m.c)] = Bc;
         // ghost chunks: periodic images, or at walls the carries of the
@@ -172,9 +197,46 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
         Yc = Yc * qL + cP[m.pslot(m.c - mm)];
         Zc = Zc * qL + cB[m.bslot(m.c + mm)];
     }
+    iir_combine<LC>(p, Yc, Zc, y, z, d);
+}
+
+// The same solve on a window of nw consecutive chunks w = 0 .. nw - 1 of a
+// row, which the caller loads with x taken periodically: every chunk
+// publishes its edge values and (w in [1, nw - 1)) its carries, and the
+// chunks w in [MC + 1, nw - MC - 1) receive the derivative.  Those chunks sum
+// the carries of exactly the MC chunks on each side that the whole-row solve
+// sums, computed from the same values, so their derivative is bitwise the
+// whole-row one.  The whole block calls it together.
+template <int LC>
+__device__ __forceinline__ void iir_solve_window(const KParams &p, int w, int nw, double qL,
+                                                 const double (&u)[LC], double *vbuf, double *cP,
+                                                 double *cB, double (&d)[LC])
+{
+    constexpr int MC = kCarry(LC);
+    if (w < nw) {
+        vbuf[4 * w + 0] = u[0];
+        vbuf[4 * w + 1] = u[1];
+        vbuf[4 * w + 2] = u[LC - 2];
+        vbuf[4 * w + 3] = u[LC - 1];
+    }
+    __syncthreads();
+    double y[LC], z[LC];
+    if (w >= 1 && w < nw - 1) {
+        double Pc, Bc;
+        iir_chunk<LC>(p, u, vbuf[4 * (w - 1) + 2], vbuf[4 * (w - 1) + 3], vbuf[4 * (w + 1)],
+                      vbuf[4 * (w + 1) + 1], y, z, Pc, Bc);
+        cP[w] = Pc;
+        cB[w] = Bc;
+    }
+    __syncthreads();
+    if (w < MC + 1 || w >= nw - MC - 1) return;
+    double Yc = 0.0, Zc = 0.0;
 #pragma unroll
-    for (int k = 0; k < LC; ++k)
-        d[k] = p.iir_K * ((y[k] + p.iir_qp[k + 1] * Yc) + (z[k] + p.iir_qp[LC - 1 - k] * Zc));
+    for (int mm = MC; mm >= 1; --mm) {
+        Yc = Yc * qL + cP[w - mm];
+        Zc = Zc * qL + cB[w + mm];
+    }
+    iir_combine<LC>(p, Yc, Zc, y, z, d);
 }
 
 // 16-byte vector access to LC consecutive doubles (32-byte aligned).
@@ -214,19 +276,40 @@ __device__ __forceinline__ Chunk<LC> row_chunk(const KParams &p, int rows)
 
 constexpr int kRowLC = 4;
 
-// Segment chunk of this thread: one segment of seg_len nodes of one row.
+// A row segment's window reaches kSegWin chunks past each end of the
+// segment in the collision pass: the chunk beyond each end, whose collision
+// gives the populations the end nodes receive; the MC chunks whose carries
+// that chunk's derivative sums; and one more, whose edge values the
+// outermost carry needs.  Pass A chains two derivatives, so its window
+// reaches kRhoWin chunks.
+constexpr int kSegWin = kCarry(kRowLC) + 2;
+constexpr int kRhoWin = 2 * (kCarry(kRowLC) + 1);
+// threads of a segment workgroup: the window's chunks, in whole waves
+constexpr int kSegThreads = ((kSegLen / kRowLC + 2 * kSegWin) + 63) / 64 * 64;
+constexpr int kRhoThreads = ((kSegLen / kRowLC + 2 * kRhoWin) + 63) / 64 * 64;
+
+// Segments of a row: ceil(nx / seg_len), the last one ragged (a whole
+// number of chunks, as nx is).
+__device__ __forceinline__ int row_segments(const KParams &p)
+{
+    return (p.nx + p.seg_len - 1) / p.seg_len;
+}
+
+// Segment chunk of this thread: thread t holds chunk t - kSegWin of a
+// segment of seg_n nodes of one row; ok marks the chunks that collide, the
+// segment's own and the one beyond each end.
 template <int LC>
-__device__ __forceinline__ Chunk<LC> seg_chunk(const KParams &p)
+__device__ __forceinline__ Chunk<LC> seg_chunk(const KParams &p, int seg_n)
 {
     Chunk<LC> m;
-    m.n = p.seg_len;
-    m.nc = p.seg_len / LC;
+    m.n = seg_n;
+    m.nc = seg_n / LC;
     m.nl = 1;
     m.col = false;
     m.mirror = false;
     m.l = 0;
-    m.c = threadIdx.x;
-    m.ok = m.c < m.nc;
+    m.c = (int)threadIdx.x - kSegWin;
+    m.ok = m.c >= -1 && m.c <= m.nc;
     return m;
 }
 
@@ -411,26 +494,42 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
 // wall), so the groups are a function of fout alone.
 //
 // SEG: the split variant for long rows.  The block holds one segment
-// [xs, xs + seg_len) of row y0 and takes F_x from fx_in (written by the
-// derivative pass k_rows_fx_iir), so it has no line solve; the density groups
-// of the segment's first and last node, which receive populations from the
-// neighbouring segments, are left to k_group_seams.
+// [xs, xs + seg_len) of row y0 and a window of kSegWin chunks on each side
+// (x periodic).  F_x comes from the row derivatives of the rho plane of pass A
+// (rho_in) and of mu over the window; the chunk beyond each end of the segment
+// also collides, without storing anything, so that the segment's end nodes
+// receive the populations that cross its ends and every density group is
+// written.  Each population is stored by the segment that owns its source
+// node.
 template <bool OBSERVE, bool KEEP, bool SEG = false, bool MRT = false>
 __device__ __forceinline__ void rows_collide_body(
     const KParams &p, int y0, const double *__restrict__ f, const double *__restrict__ mu,
     const double *__restrict__ fy, double *__restrict__ fout, double *__restrict__ gout,
     double *__restrict__ o_rho, double *__restrict__ o_vx, double *__restrict__ o_vy,
-    double *__restrict__ o_fx, int xs = 0, const double *__restrict__ fx_in = nullptr)
+    double *__restrict__ o_fx, int xs = 0, const double *__restrict__ rho_in = nullptr,
+    int seg_n = 0)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
     const size_t N = (size_t)nx * ny;
     const int rows = SEG ? 1 : min(p.rows_per_block, ny - y0);
-    const Chunk<LC> m = SEG ? seg_chunk<LC>(p) : row_chunk<LC>(p, rows);
-    const int nlc = SEG ? m.nc : p.rows_per_block * m.nc;
-    const LineLds L = carve_lds(smem, m);
-    const int y = y0 + m.l, x0 = xs + m.c * LC;
+    const Chunk<LC> m = SEG ? seg_chunk<LC>(p, seg_n) : row_chunk<LC>(p, rows);
+    // SEG: the window's chunks; LDS holds the window solve (edges, carries)
+    // and then the edge exchange of the density groups
+    const int nw = m.nc + 2 * kSegWin;
+    const int nlc = SEG ? nw : p.rows_per_block * m.nc;
+    LineLds L;
+    if (SEG) {
+        L.vbuf = smem;
+        L.cP = smem + 4 * nw;
+        L.cB = L.cP + nw;
+        L.edge = L.cB + nw;
+    } else {
+        L = carve_lds(smem, m);
+    }
+    const int xc = xs + m.c * LC;
+    const int y = y0 + m.l, x0 = !SEG ? xc : (xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc));
     const size_t base = (size_t)y * nx + x0;
     constexpr int NI = KEEP ? 9 : 1;
     double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
@@ -467,9 +566,21 @@ __device__ __forceinline__ void rows_collide_body(
     }
     double Fy[LC], Fx[LC];
     if (SEG) {
+        // F_x of Eq. 12 (or of the pseudopotential model) from the planes,
+        // bitwise as a whole-row derivative pass over them would give it
+        const int w = threadIdx.x;
+        double r[LC], u[LC], dxr[LC], dxm[LC];
+        if (w < nw) {
+            vload<LC>(rho_in + base, r);
+            vload<LC>(mu + base, u);
+        }
+        if (!p.sc) iir_solve_window<LC>(p, w, nw, p.iir_qL_row, r, L.vbuf, L.cP, L.cB, dxr);
+        iir_solve_window<LC>(p, w, nw, p.iir_qL_row, u, L.vbuf, L.cP, L.cB, dxm);
         if (m.ok) {
             vload<LC>(fy + base, Fy);
-            vload<LC>(fx_in + base, Fx);
+#pragma unroll
+            for (int k = 0; k < LC; ++k)
+                Fx[k] = p.sc ? CS2 * u[k] * dxm[k] : -r[k] * dxm[k] + CS2 * dxr[k];
         }
     } else {
         // F_x of Eq. 12, or of the pseudopotential model (mv holds psi)
@@ -484,7 +595,7 @@ __device__ __forceinline__ void rows_collide_body(
         }
     }
     if (OBSERVE) {
-        if (!m.ok) return;
+        if (!m.ok || (SEG && (m.c < 0 || m.c >= m.nc))) return;
 #pragma unroll
         for (int k = 0; k < LC; ++k) {
             const double rh = rho[k], ir = 1.0 / rh;
@@ -501,7 +612,9 @@ __device__ __forceinline__ void rows_collide_body(
     // receives from the left neighbour (populations 1, 5, 8) and its last
     // node from the right neighbour (3, 6, 7), six slots per chunk.
     double *edge = L.edge;
-    const int slot = m.l * m.nc + m.c;
+    const int slot = SEG ? (int)threadIdx.x : m.l * m.nc + m.c;
+    // SEG: the chunks beyond the segment's ends only supply edge values
+    const bool store = !SEG || (m.c >= 0 && m.c < m.nc);
     // the row's down-going groups bounce back at a bottom wall, the
     // up-going ones at a top wall
     const bool refl_d = p.bc_y && y == 0, refl_u = p.bc_y && y == ny - 1;
@@ -639,6 +752,7 @@ __device__ __forceinline__ void rows_collide_body(
                 break;
             default: break;
             }
+            if (!store) continue;
             if (refl) {
                 vstore<LC>(fout + OPP[i] * N + base, v);
                 continue;
@@ -697,11 +811,12 @@ __device__ __forceinline__ void rows_collide_body(
         }
     }
     __syncthreads();
-    if (!m.ok) return;
-    // x is periodic: the neighbours of the first and last chunk wrap
+    if (!m.ok || !store) return;
+    // x is periodic: the neighbours of the first and last chunk wrap (in a
+    // segment they are the window's chunks beyond its ends)
     const int row0 = m.l * m.nc;
-    const int left = row0 + (m.c > 0 ? m.c - 1 : m.nc - 1);
-    const int right = row0 + (m.c < m.nc - 1 ? m.c + 1 : 0);
+    const int left = SEG ? slot - 1 : row0 + (m.c > 0 ? m.c - 1 : m.nc - 1);
+    const int right = SEG ? slot + 1 : row0 + (m.c < m.nc - 1 ? m.c + 1 : 0);
     gm[0] = (gm[0] + edge[0 * nlc + left]) + hm;
     gm[LC - 1] += edge[1 * nlc + right];
     if (!refl_u) {
@@ -716,16 +831,6 @@ __device__ __forceinline__ void rows_collide_body(
     // g2); g2 of the row below (of this row at a bottom wall, as g1)
     const size_t up = refl_u ? 2 * N + base : N + (size_t)(y + 1 < ny ? y + 1 : 0) * nx + x0;
     const size_t dn = refl_d ? N + base : 2 * N + (size_t)(y > 0 ? y - 1 : ny - 1) * nx + x0;
-    if (SEG && (m.c == 0 || m.c == m.nc - 1)) {
-        // a segment's end node: its groups come from k_group_seams
-        const int k0 = m.c == 0 ? 1 : 0, k1 = m.c == m.nc - 1 ? LC - 1 : LC;
-        for (int k = k0; k < k1; ++k) {
-            gout[base + k] = gm[k];
-            gout[up + k] = gu[k];
-            gout[dn + k] = gd[k];
-        }
-        return;
-    }
     vstore<LC>(gout + base, gm);
     vstore<LC>(gout + up, gu);
     vstore<LC>(gout + dn, gd);
@@ -742,78 +847,93 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide_iir(
                                                  fout, gout, o_rho, o_vx, o_vy, o_fx);
 }
 
-// ---- split collision pass for long rows -------------------------------
+// ---- row segments: the split collision pass, and long rows -------------
 // Rows longer than one 256-thread workgroup holds with the populations in
-// registers run pass C as two kernels: the row derivatives and F_x over whole
-// rows (k_rows_fx_iir), then the collision without a line solve over equal
-// row segments of at most 1024 nodes (seg_len) in workgroups of at most 256
-// threads that hold f in registers (k_collide_seg_iir); k_group_seams then
-// forms the density groups of the segments' end nodes from the finished f.
+// registers may run pass C over row segments of kSegLen nodes (the last one
+// ragged), one workgroup per segment that holds f in registers.  Each
+// workgroup takes the row derivatives over its segment's window (the
+// segment and kSegWin chunks on each side, x periodic), so the pass stays
+// one kernel and every density group is written.  Rows longer than one
+// workgroup holds at all (more than 4096 nodes) also run pass A and the
+// observation pass over windowed segments.
 
-// F_x = -rho d/dx mu + c_s^2 d/dx rho (Eq. 12) from the rho and mu planes
-// (pseudopotential model: c_s^2 psi d/dx psi, psi in the mu plane).
-__device__ __forceinline__ void rows_fx_body(const KParams &p, int y0,
-                                             const double *__restrict__ rho,
-                                             const double *__restrict__ mu,
-                                             double *__restrict__ fx_out)
+template <bool KEEP, bool MRT>
+__global__ __launch_bounds__(kSegThreads) void k_collide_seg_iir(
+    KParams p, const double *__restrict__ f, const double *__restrict__ rho,
+    const double *__restrict__ mu, const double *__restrict__ fy, double *__restrict__ fout,
+    double *__restrict__ gout)
+{
+    const int nseg = row_segments(p);
+    const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
+    const int xs = sg * p.seg_len;
+    rows_collide_body<false, KEEP, true, MRT>(p, y, f, mu, fy, fout, gout, nullptr, nullptr,
+                                              nullptr, nullptr, xs, rho,
+                                              min(p.seg_len, p.nx - xs));
+}
+
+// Observation (rho, v, F_x of the current state) over row segments.
+__global__ __launch_bounds__(kSegThreads) void k_observe_seg_iir(
+    KParams p, const double *__restrict__ f, const double *__restrict__ rho,
+    const double *__restrict__ mu, const double *__restrict__ fy, double *__restrict__ o_rho,
+    double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
+{
+    const int nseg = row_segments(p);
+    const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
+    const int xs = sg * p.seg_len;
+    rows_collide_body<true, false, true, false>(p, y, f, mu, fy, nullptr, nullptr, o_rho, o_vx,
+                                                o_vy, o_fx, xs, rho, min(p.seg_len, p.nx - xs));
+}
+
+// Pass A over a row segment of seg_n nodes and a window of kRhoWin chunks on
+// each side (rows longer than one workgroup holds): the same values as the
+// whole-row pass, since each derivative sums the carries of exactly MC chunks
+// on each side, computed from the same values.
+template <bool SC>
+__global__ __launch_bounds__(kRhoThreads) void k_rows_rho_seg_iir(KParams p,
+                                                                  const double *__restrict__ g,
+                                                                  double *__restrict__ rho_out,
+                                                                  double *__restrict__ mux_out)
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
-    const int rows = min(p.rows_per_block, p.ny - y0);
-    const Chunk<LC> m = row_chunk<LC>(p, rows);
-    const LineLds L = carve_lds(smem, m);
-    const size_t base = (size_t)(y0 + m.l) * p.nx + m.c * LC;
-    double r[LC], mv[LC];
-    if (m.ok) {
-        vload<LC>(rho + base, r);
-        vload<LC>(mu + base, mv);
-    }
-    double dxr[LC], dxm[LC];
-    if (!p.sc) iir_solve<LC>(p, m, p.iir_qL_row, r, 1.0, L, dxr);
-    iir_solve<LC>(p, m, p.iir_qL_row, mv, 1.0, L, dxm);
-    if (m.ok) {
-        double Fx[LC];
-#pragma unroll
-        for (int k = 0; k < LC; ++k)
-            Fx[k] = p.sc ? CS2 * mv[k] * dxm[k] : -r[k] * dxm[k] + CS2 * dxr[k];
-        vstore<LC>(fx_out + base, Fx);
-    }
-}
-
-template <int MAXT>
-__global__ __launch_bounds__(MAXT) void k_rows_fx_iir(KParams p, const double *__restrict__ rho,
-                                                      const double *__restrict__ mu,
-                                                      double *__restrict__ fx_out)
-{
-    rows_fx_body(p, blockIdx.x * p.rows_per_block, rho, mu, fx_out);
-}
-
-template <bool KEEP, bool MRT>
-__global__ __launch_bounds__(256) void k_collide_seg_iir(
-    KParams p, const double *__restrict__ f, const double *__restrict__ fy,
-    const double *__restrict__ fx, double *__restrict__ fout, double *__restrict__ gout)
-{
-    const int nseg = p.nx / p.seg_len;
+    const int nseg = row_segments(p);
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
-    rows_collide_body<false, KEEP, true, MRT>(p, y, f, nullptr, fy, fout, gout, nullptr,
-                                              nullptr, nullptr, nullptr, sg * p.seg_len, fx);
-}
-
-// Density groups (as k_density_groups) at the first and last node of every
-// segment of every row.
-__global__ void k_group_seams(KParams p, const double *__restrict__ f, double *__restrict__ g)
-{
-    const int nseg = p.nx / p.seg_len;
-    const size_t N = (size_t)p.nx * p.ny, total = (size_t)p.ny * nseg * 2;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-         i += (size_t)gridDim.x * blockDim.x) {
-        const size_t y = i / (2 * nseg);
-        const int j = (int)(i - y * 2 * nseg);
-        const int x = (j >> 1) * p.seg_len + ((j & 1) ? p.seg_len - 1 : 0);
-        const size_t n = y * p.nx + x;
-        g[n] = (f[n] + f[N + n]) + f[3 * N + n];
-        g[N + n] = (f[2 * N + n] + f[5 * N + n]) + f[6 * N + n];
-        g[2 * N + n] = (f[4 * N + n] + f[7 * N + n]) + f[8 * N + n];
+    const int xs = sg * p.seg_len, nc = min(p.seg_len, p.nx - xs) / LC;
+    const int nx = p.nx, w = threadIdx.x, nw = nc + 2 * kRhoWin, c = w - kRhoWin;
+    const size_t N = (size_t)nx * p.ny;
+    const int xc = xs + c * LC;
+    const int x0 = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
+    const size_t base = (size_t)y * nx + x0;
+    const bool core = c >= 0 && c < nc;
+    double *vbuf = smem, *cP = smem + 4 * nw, *cB = cP + nw;
+    double rho[LC], mx[LC];
+    if (w < nw) {
+        double g0[LC], g1[LC], g2[LC];
+        vload<LC>(g + base, g0);
+        vload<LC>(g + N + base, g1);
+        vload<LC>(g + 2 * N + base, g2);
+#pragma unroll
+        for (int k = 0; k < LC; ++k) rho[k] = (g0[k] + g1[k]) + g2[k];
+        if (core) {
+            vstore<LC>(rho_out + base, rho);
+#pragma unroll
+            for (int k = 0; k < LC; ++k)
+                mx[k] = SC ? sc_psi(p, rho[k]) : p.k2 * mu0_capped(p, rho[k]);
+        }
+    }
+    if (p.kappa_zero || SC) {
+        if (core) vstore<LC>(mux_out + base, mx);
+        return;
+    }
+    double d1[LC], d2[LC];
+#pragma unroll
+    for (int k = 0; k < LC; ++k) d1[k] = 0.0;
+    iir_solve_window<LC>(p, w, nw, p.iir_qL_row, rho, vbuf, cP, cB, d1);
+    iir_solve_window<LC>(p, w, nw, p.iir_qL_row, d1, vbuf, cP, cB, d2);
+    if (core) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) mx[k] -= p.kappa * d2[k];
+        vstore<LC>(mux_out + base, mx);
     }
 }
 
@@ -982,26 +1102,57 @@ hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double 
 
 bool iir_split_ok(const KParams &p)
 {
-    return p.use_iir_rows && p.nx > kSegLen && p.seg_len > 0 && p.nx % p.seg_len == 0 &&
-           p.seg_len % kRowLC == 0 && p.seg_len <= kSegLen && p.nx / p.seg_len >= 2;
+    return p.nx > kSegLen && p.nx % kRowLC == 0 && p.seg_len == kSegLen &&
+           p.iir_m_row <= kCarry(kRowLC);
 }
 
-hipError_t launch_rows_fx_iir(const KParams &p, const double *rho, const double *mu, double *fx,
-                              hipStream_t s)
+// Workgroups of a segment kernel: one per segment of every row, threads for
+// the widest window.
+static int seg_blocks(const KParams &p) { return p.ny * ((p.nx + p.seg_len - 1) / p.seg_len); }
+static int seg_threads(const KParams &p, int win)
 {
-    const int T = row_threads_iir(p);
-#define ARGS dim3(row_blocks(p)), dim3(T), row_lds_iir(p, false), s, p, rho, mu, fx
-    CPLBM_IIR_THREADS(T, k_rows_fx_iir<256>, k_rows_fx_iir<1024>, ARGS);
+    return ((p.seg_len / kRowLC + 2 * win) + 63) / 64 * 64;
+}
+
+hipError_t launch_rows_rho_seg_iir(const KParams &p, const double *g, double *rho, double *mux,
+                                   hipStream_t s)
+{
+    if (!iir_split_ok(p)) return hipErrorInvalidValue;
+    const int nw = p.seg_len / kRowLC + 2 * kRhoWin;
+    const size_t lds = sizeof(double) * 6 * (size_t)nw;
+#define ARGS dim3(seg_blocks(p)), dim3(seg_threads(p, kRhoWin)), lds, s, p, g, rho, mux
+    if (p.sc)
+        hipLaunchKernelGGL((k_rows_rho_seg_iir<true>), ARGS);
+    else
+        hipLaunchKernelGGL((k_rows_rho_seg_iir<false>), ARGS);
 #undef ARGS
     return hipGetLastError();
 }
 
-hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const double *fy,
-                                  const double *fx, double *fout, double *gout, hipStream_t s)
+hipError_t launch_observe_seg_iir(const KParams &p, const double *f, const double *rho,
+                                  const double *mu, const double *fy, double *o_rho, double *o_vx,
+                                  double *o_vy, double *o_fx, hipStream_t s)
 {
-    const int S = p.seg_len, blocks = p.ny * (p.nx / S);
-    const size_t lds = line_lds(S, 1, kRowLC, true);
-#define ARGS dim3(blocks), dim3(S / kRowLC), lds, s, p, f, fy, fx, fout, gout
+    if (!iir_split_ok(p)) return hipErrorInvalidValue;
+    const int nw = p.seg_len / kRowLC + 2 * kSegWin;
+    const size_t lds = sizeof(double) * 12 * (size_t)nw;
+    hipLaunchKernelGGL(k_observe_seg_iir, dim3(seg_blocks(p)), dim3(seg_threads(p, kSegWin)),
+                       lds, s, p, f, rho, mu, fy, o_rho, o_vx, o_vy, o_fx);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
+                                    const double *mu, const double *fy, double *fout,
+                                    double *gout, hipStream_t s)
+{
+    if (!iir_split_ok(p)) return hipErrorInvalidValue;
+    const int S = p.seg_len, blocks = seg_blocks(p);
+    const int nw = S / kRowLC + 2 * kSegWin;
+    const int T = seg_threads(p, kSegWin);
+    // the window solve's edges and carries (4 + 2 per chunk), then the six
+    // edge planes of the density groups
+    const size_t lds = sizeof(double) * 12 * (size_t)nw;
+#define ARGS dim3(blocks), dim3(T), lds, s, p, f, rho, mu, fy, fout, gout
     if (p.row_keep && p.mrt)
         hipLaunchKernelGGL((k_collide_seg_iir<true, true>), ARGS);
     else if (p.row_keep)
@@ -1012,26 +1163,6 @@ hipError_t launch_collide_seg_iir(const KParams &p, const double *f, const doubl
         hipLaunchKernelGGL((k_collide_seg_iir<false, false>), ARGS);
 #undef ARGS
     return hipGetLastError();
-}
-
-hipError_t launch_group_seams(const KParams &p, const double *fout, double *gout, hipStream_t s)
-{
-    const size_t seams = (size_t)p.ny * (p.nx / p.seg_len) * 2;
-    // one wave per workgroup, so that the few seam nodes spread over every CU
-    hipLaunchKernelGGL(k_group_seams, dim3((unsigned)((seams + 63) / 64)), dim3(64), 0, s, p,
-                       fout, gout);
-    return hipGetLastError();
-}
-
-hipError_t launch_collide_split_iir(const KParams &p, const double *f, const double *rho,
-                                    const double *mu, const double *fy, double *fx,
-                                    double *fout, double *gout, hipStream_t s)
-{
-    if (!iir_split_ok(p)) return hipErrorInvalidValue;
-    hipError_t e = launch_rows_fx_iir(p, rho, mu, fx, s);
-    if (e == hipSuccess) e = launch_collide_seg_iir(p, f, fy, fx, fout, gout, s);
-    if (e == hipSuccess) e = launch_group_seams(p, fout, gout, s);
-    return e;
 }
 
 hipError_t launch_rows_collide_iir(const KParams &p, const double *f, const double *mu,

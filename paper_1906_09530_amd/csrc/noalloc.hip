@@ -15,17 +15,16 @@ namespace {
 
 // Largest mesh the allocation-free entry point takes (nx * ny nodes), and
 // the planes of scratch it carves: the spare f (9), the density groups of
-// both buffers (2 x 3), rho, the row part of mu, mu, F_y and the F_x plane
-// of the split collision pass (5).
+// both buffers (2 x 3), rho, the row part of mu, mu and F_y (4).
 constexpr size_t kMaxNodes = LBM_NOALLOC_MAX_NODES;
 constexpr size_t kPlaneBytes = kMaxNodes * sizeof(double);  // a multiple of 256
-constexpr size_t kScratchPlanes = 9 + 6 + 5;
+constexpr size_t kScratchPlanes = 9 + 6 + 4;
 constexpr size_t kScratchBytes = kScratchPlanes * kPlaneBytes;
 constexpr int kMaxDevices = 64;
 
 }  // namespace
 
-// 40 MiB per device.  In host code `scratch` names a host-side stand-in,
+// 38 MiB per device.  In host code `scratch` names a host-side stand-in,
 // not device memory: kernels receive the address hipGetSymbolAddress gives
 // for the current device.
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -90,7 +89,6 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_params *p, double *f, int64_t n
     double *g[2] = {(double *)(base + 9 * plane), (double *)(base + 12 * plane)};
     double *rho = (double *)(base + 15 * plane), *mux = (double *)(base + 16 * plane);
     double *mu = (double *)(base + 17 * plane), *fy = (double *)(base + 18 * plane);
-    double *fx = (double *)(base + 19 * plane);
     hipStream_t s = (hipStream_t)hip_stream;
 
     // the same sequence as lbm_step, the state alternating between the
@@ -104,7 +102,7 @@ extern "C" lbm_status lbm_step_noalloc(const lbm_params *p, double *f, int64_t n
         e = launch_rows_rho(kp, fb[cur], g[cur], rho, mux, s);
         if (e == hipSuccess) e = launch_cols_mu(kp, rho, mux, mu, fy, s);
         if (e == hipSuccess)
-            e = launch_rows_collide(kp, fb[cur], mu, fy, fb[1 - cur], g[1 - cur], rho, fx, s);
+            e = launch_rows_collide(kp, fb[cur], mu, fy, fb[1 - cur], g[1 - cur], rho, s);
         cur = 1 - cur;
     }
     if (e == hipSuccess && cur == 1)

@@ -277,8 +277,8 @@ class Solver:
 
     def time_step_kernels(self, n):
         """Average ms of each kernel over n real steps (events around every
-        launch inside the sequence); 3 kernels, or 5 with the split pass."""
-        ms = (C.c_double * 5)()
+        launch inside the sequence): row pass A, column pass B, collision."""
+        ms = (C.c_double * 3)()
         cnt = C.c_int()
         _check(load().lbm_time_step_kernels(self.ctx, int(n), ms, C.byref(cnt)), self.ctx)
         return list(ms)[:cnt.value]

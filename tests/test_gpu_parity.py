@@ -567,3 +567,55 @@ def test_graph_replay_matches_launches(case):
     assert a.steps_taken == b.steps_taken == 162
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(4608, 40, 0), (5000, 32, 1)])
+def test_rows_longer_than_a_workgroup(nx, ny, walls):
+    """Rows beyond 4096 nodes run every row pass over 512-node segments with
+    windows (5000 = 9 x 512 + 392: a ragged last segment): parity with the
+    oracle after 60 and 120 steps, the observation pass (mu, F of Eqs. 12
+    and 33) at the start, and a resumed run ends bitwise where the
+    uninterrupted one does."""
+    p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                         bc_y=walls, wall_ux=0.01 if walls else 0.0)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, ny / 3.0, 3.0, seed=31, noise=1e-4,
+                                    center=(nx - 20.5, ny / 2.0))
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    mu, fx, fy = s.force_fields()
+    f = oracle.init(op, rho0, ux0, uy0)
+    _, _, _, mu2, fx2, fy2 = oracle.moments(op, f, want_force=True)
+    assert np.abs(mu - mu2).max() <= 1e-12 * np.abs(mu2).max()
+    fm = max(np.abs(fx2).max(), np.abs(fy2).max())
+    assert np.abs(fx - fx2).max() <= 1e-12 * fm
+    assert np.abs(fy - fy2).max() <= 1e-12 * fm
+    ref = _oracle_after(op, rho0, ux0, uy0, [60, 120])
+    s.step(60)
+    mid = s.get_state()
+    er, ev = _errors(s.moments(), ref[60])
+    s.step(60)
+    er2, ev2 = _errors(s.moments(), ref[120])
+    print("\nlong rows %dx%d walls=%d: rho %.2e %.2e, v %.2e %.2e" % (nx, ny, walls, er, er2,
+                                                                    ev, ev2))
+    assert max(er, er2, ev, ev2) <= TOL
+    b = lbm.Solver(p, rho0, ux0, uy0)
+    b.set_state(mid)
+    b.step(60)
+    np.testing.assert_array_equal(b.get_state(), s.get_state())
+    for v in (0, 1):
+        with pytest.raises(lbm.LBMError):
+            b.set_collision_variant(v)
+    s.close()
+    b.close()
+
+
+@pytest.mark.parametrize("nx,ny,walls", [(16, 5000, 0), (24, 9216, 1)])
+def test_columns_longer_than_a_workgroup_reduction(nx, ny, walls):
+    """Columns beyond 4096 nodes take the factorised solve with 8-node chunks
+    (up to 8192) or 16-node chunks (beyond): parity with the oracle after 40
+    steps."""
+    p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
+                         bc_y=walls)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 3.0, seed=5, noise=1e-4)
+    _run_case("longcols%dx%d" % (nx, ny), p, op, rho0, ux0, uy0, [40])
