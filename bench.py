@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0
 #   column pass B: read rho and the row part of mu; write mu, F_y
 #   row pass C: read f (9 x 8), mu, F_y; write f (9 x 8) and its three
 #     density groups (3 x 8); over row segments (long rows) it also reads
-#     rho (8), and the window's 52 nodes past each end of a 512-node segment
-#     add ~3 B of rho and mu reads
+#     rho (8), and the window's 52 nodes past each end of an 896-node
+#     segment add ~2 B of rho and mu reads
 # and, for the roofline, the algorithmic count of the collide-and-stream
 # kernel: read f and the two force or chemical-potential inputs, write f
 # (72 + 24 + 72 = 168 B per lattice update); the floor of any scheme is f
@@ -493,6 +493,9 @@ def main():
                     help="the 4096 x 2048 splash between walls: its whole-step rate and "
                          "in-sequence kernel times, the roofline point (hbm, default); also "
                          "the 10,000-step run in two frames (full, about 20 s more); or none")
+    ap.add_argument("--small", choices=["64", "none"], default="64",
+                    help="the 64 x 64 drop of 2000 steps, launched kernel by kernel and from "
+                         "captured graphs (64, default), or none")
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="steps over which each kernel is timed inside the sequence")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -573,8 +576,10 @@ def main():
         splash = splash_hbm(torch, lbm, inputs, kernel_steps=args.kernel_steps)
         if args.splash == "full":
             splash["two_frames_10000_steps"] = splash_bench(torch, lbm, inputs)
-    print("64 x 64 drop: launches one by one and from graphs", file=sys.stderr, flush=True)
-    small = small_mesh_bench(torch, lbm, inputs)
+    small = None
+    if args.small != "none":
+        print("64 x 64 drop: launches one by one and from graphs", file=sys.stderr, flush=True)
+        small = small_mesh_bench(torch, lbm, inputs)
     copy_big_gbs = copy_bandwidth(torch, 2 << 30, reps=5)
     sweep = None if args.sweep == "none" else sweep_bench(lbm, inputs, args.sweep)
     warm = None if args.warmstart == "none" else warmstart_bench(args.warmstart)

@@ -232,7 +232,7 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, dou
  *   0  one kernel over whole rows, reading the populations twice;
  *   1  one kernel over whole rows holding the populations in registers
  *      (rows of at most 1024 nodes; the default there);
- *   2  over row segments of 512 nodes (rows longer than 512 nodes, a
+ *   2  over row segments of 896 nodes (rows longer than 896 nodes, a
  *      multiple of 4; the last segment may be shorter): one workgroup per
  *      segment holds its populations in registers and takes F_x from the
  *      density and mu planes over a window of 52 nodes past each end of the

@@ -52,7 +52,9 @@ struct KParams {
 };
 
 constexpr int kIirRowChunk = 4;
-constexpr int kSegLen = 512;          // row segment of the segment kernels
+// row segment of the segment kernels: 224 chunks, which with the collision
+// window's 26 fill a 256-thread workgroup
+constexpr int kSegLen = 896;
 constexpr int kMaxWholeRow = 4096;    // longest row one workgroup holds
 
 int row_blocks(const KParams &p);

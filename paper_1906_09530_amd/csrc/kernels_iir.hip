@@ -284,15 +284,18 @@ constexpr int kRowLC = 4;
 // reaches kRhoWin chunks.
 constexpr int kSegWin = kCarry(kRowLC) + 2;
 constexpr int kRhoWin = 2 * (kCarry(kRowLC) + 1);
+// pass A's segments: 208 chunks, which with its window's 48 fill a
+// 256-thread workgroup
+constexpr int kRhoSegLen = 832;
 // threads of a segment workgroup: the window's chunks, in whole waves
 constexpr int kSegThreads = ((kSegLen / kRowLC + 2 * kSegWin) + 63) / 64 * 64;
-constexpr int kRhoThreads = ((kSegLen / kRowLC + 2 * kRhoWin) + 63) / 64 * 64;
+constexpr int kRhoThreads = ((kRhoSegLen / kRowLC + 2 * kRhoWin) + 63) / 64 * 64;
 
-// Segments of a row: ceil(nx / seg_len), the last one ragged (a whole
-// number of chunks, as nx is).
-__device__ __forceinline__ int row_segments(const KParams &p)
+// Segments of len nodes in a row: ceil(nx / len), the last one ragged (a
+// whole number of chunks, as nx is).
+__device__ __forceinline__ int row_segments(const KParams &p, int len)
 {
-    return (p.nx + p.seg_len - 1) / p.seg_len;
+    return (p.nx + len - 1) / len;
 }
 
 // Segment chunk of this thread: thread t holds chunk t - kSegWin of a
@@ -863,7 +866,7 @@ __global__ __launch_bounds__(kSegThreads) void k_collide_seg_iir(
     const double *__restrict__ mu, const double *__restrict__ fy, double *__restrict__ fout,
     double *__restrict__ gout)
 {
-    const int nseg = row_segments(p);
+    const int nseg = row_segments(p, p.seg_len);
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
     const int xs = sg * p.seg_len;
     rows_collide_body<false, KEEP, true, MRT>(p, y, f, mu, fy, fout, gout, nullptr, nullptr,
@@ -877,15 +880,15 @@ __global__ __launch_bounds__(kSegThreads) void k_observe_seg_iir(
     const double *__restrict__ mu, const double *__restrict__ fy, double *__restrict__ o_rho,
     double *__restrict__ o_vx, double *__restrict__ o_vy, double *__restrict__ o_fx)
 {
-    const int nseg = row_segments(p);
+    const int nseg = row_segments(p, p.seg_len);
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
     const int xs = sg * p.seg_len;
     rows_collide_body<true, false, true, false>(p, y, f, mu, fy, nullptr, nullptr, o_rho, o_vx,
                                                 o_vy, o_fx, xs, rho, min(p.seg_len, p.nx - xs));
 }
 
-// Pass A over a row segment of seg_n nodes and a window of kRhoWin chunks on
-// each side (rows longer than one workgroup holds): the same values as the
+// Pass A over a row segment of kRhoSegLen nodes (the last one ragged) and a
+// window of kRhoWin chunks on each side (rows longer than one workgroup holds): the same values as the
 // whole-row pass, since each derivative sums the carries of exactly MC chunks
 // on each side, computed from the same values.
 template <bool SC>
@@ -896,9 +899,9 @@ __global__ __launch_bounds__(kRhoThreads) void k_rows_rho_seg_iir(KParams p,
 {
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
-    const int nseg = row_segments(p);
+    const int nseg = row_segments(p, kRhoSegLen);
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
-    const int xs = sg * p.seg_len, nc = min(p.seg_len, p.nx - xs) / LC;
+    const int xs = sg * kRhoSegLen, nc = min(kRhoSegLen, p.nx - xs) / LC;
     const int nx = p.nx, w = threadIdx.x, nw = nc + 2 * kRhoWin, c = w - kRhoWin;
     const size_t N = (size_t)nx * p.ny;
     const int xc = xs + c * LC;
@@ -1106,21 +1109,20 @@ bool iir_split_ok(const KParams &p)
            p.iir_m_row <= kCarry(kRowLC);
 }
 
-// Workgroups of a segment kernel: one per segment of every row, threads for
-// the widest window.
-static int seg_blocks(const KParams &p) { return p.ny * ((p.nx + p.seg_len - 1) / p.seg_len); }
-static int seg_threads(const KParams &p, int win)
-{
-    return ((p.seg_len / kRowLC + 2 * win) + 63) / 64 * 64;
-}
+// Workgroups of a segment kernel (segments of len nodes): one per segment
+// of every row, threads for the widest window.
+static int seg_blocks(const KParams &p, int len) { return p.ny * ((p.nx + len - 1) / len); }
+static int seg_threads(int len, int win) { return ((len / kRowLC + 2 * win) + 63) / 64 * 64; }
 
 hipError_t launch_rows_rho_seg_iir(const KParams &p, const double *g, double *rho, double *mux,
                                    hipStream_t s)
 {
     if (!iir_split_ok(p)) return hipErrorInvalidValue;
-    const int nw = p.seg_len / kRowLC + 2 * kRhoWin;
+    const int nw = kRhoSegLen / kRowLC + 2 * kRhoWin;
     const size_t lds = sizeof(double) * 6 * (size_t)nw;
-#define ARGS dim3(seg_blocks(p)), dim3(seg_threads(p, kRhoWin)), lds, s, p, g, rho, mux
+#define ARGS                                                                                   \
+    dim3(seg_blocks(p, kRhoSegLen)), dim3(seg_threads(kRhoSegLen, kRhoWin)), lds, s, p, g, rho, \
+        mux
     if (p.sc)
         hipLaunchKernelGGL((k_rows_rho_seg_iir<true>), ARGS);
     else
@@ -1136,8 +1138,9 @@ hipError_t launch_observe_seg_iir(const KParams &p, const double *f, const doubl
     if (!iir_split_ok(p)) return hipErrorInvalidValue;
     const int nw = p.seg_len / kRowLC + 2 * kSegWin;
     const size_t lds = sizeof(double) * 12 * (size_t)nw;
-    hipLaunchKernelGGL(k_observe_seg_iir, dim3(seg_blocks(p)), dim3(seg_threads(p, kSegWin)),
-                       lds, s, p, f, rho, mu, fy, o_rho, o_vx, o_vy, o_fx);
+    hipLaunchKernelGGL(k_observe_seg_iir, dim3(seg_blocks(p, p.seg_len)),
+                       dim3(seg_threads(p.seg_len, kSegWin)), lds, s, p, f, rho, mu, fy, o_rho,
+                       o_vx, o_vy, o_fx);
     return hipGetLastError();
 }
 
@@ -1146,9 +1149,9 @@ hipError_t launch_collide_split_iir(const KParams &p, const double *f, const dou
                                     double *gout, hipStream_t s)
 {
     if (!iir_split_ok(p)) return hipErrorInvalidValue;
-    const int S = p.seg_len, blocks = seg_blocks(p);
+    const int S = p.seg_len, blocks = seg_blocks(p, S);
     const int nw = S / kRowLC + 2 * kSegWin;
-    const int T = seg_threads(p, kSegWin);
+    const int T = seg_threads(S, kSegWin);
     // the window solve's edges and carries (4 + 2 per chunk), then the six
     // edge planes of the density groups
     const size_t lds = sizeof(double) * 12 * (size_t)nw;

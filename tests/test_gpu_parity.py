@@ -412,13 +412,13 @@ def test_other_equations_of_state(eos):
 @pytest.mark.parametrize("nx,ny,walls", [(2048, 48, 0), (3072, 40, 1), (1536, 40, 1),
                                          (3000, 32, 0)])
 def test_split_collision_for_long_rows(nx, ny, walls):
-    """The split collision variant (F_x over whole rows, then the collision
-    over equal row segments of at most 1024 nodes -- 1024, 1024, 768 and 1000
-    here -- then the density groups of the segments' end nodes): parity with
-    the oracle after 100 and 200 steps; a run resumed
-    from its own state ends bitwise where the uninterrupted one does (the
-    groups formed at the seams equal those of f); and the whole-row variant
-    agrees to round-off, also when a run switches to it after split steps."""
+    """The segment collision variant (896-node row segments, the last one
+    ragged -- 256, 384, 640 and 312 nodes here -- each with F_x over a window
+    past its ends and the chunk beyond each end collided for the end nodes'
+    density groups): parity with the oracle after 100 and 200 steps; a run
+    resumed from its own state ends bitwise where the uninterrupted one does;
+    and the whole-row variant agrees to round-off, also when a run switches
+    to it after segment steps."""
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls)
     g, l = A.coexistence(p.eos, p.T_r)
@@ -571,11 +571,12 @@ def test_graph_replay_matches_launches(case):
 
 @pytest.mark.parametrize("nx,ny,walls", [(4608, 40, 0), (5000, 32, 1)])
 def test_rows_longer_than_a_workgroup(nx, ny, walls):
-    """Rows beyond 4096 nodes run every row pass over 512-node segments with
-    windows (5000 = 9 x 512 + 392: a ragged last segment): parity with the
-    oracle after 60 and 120 steps, the observation pass (mu, F of Eqs. 12
-    and 33) at the start, and a resumed run ends bitwise where the
-    uninterrupted one does."""
+    """Rows beyond 4096 nodes run every row pass over segments with windows
+    (collision and observation: 896-node segments, 5000 = 5 x 896 + 520;
+    pass A: 832-node segments, 5000 = 6 x 832 + 8, a last segment of two
+    chunks): parity with the oracle after 60 and 120 steps, the observation
+    pass (mu, F of Eqs. 12 and 33) at the start, and a resumed run ends
+    bitwise where the uninterrupted one does."""
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls, wall_ux=0.01 if walls else 0.0)
     g, l = A.coexistence(p.eos, p.T_r)
