@@ -80,12 +80,14 @@ def slab(nx, ny, rho_g, rho_l, width, *, seed=0, noise=0.0):
 
 
 def splash(nx, ny, rho_g, rho_l, radius, width, *, film=40, drop_center=None, drop_uy=-0.05,
-           frame_ux=0.0):
+           frame_ux=0.0, smooth_velocity=False):
     """Drop falling onto a liquid film lying on the bottom wall: film for
     y < `film`, drop of radius `radius` centred at `drop_center` (default
     (nx/2, film + radius + 10)).  The drop moves with (0, drop_uy) where its
-    liquid fraction exceeds one half; `frame_ux` is added to every node
-    (reference frame moving to the right)."""
+    liquid fraction exceeds one half, or (smooth_velocity) with drop_uy times
+    its liquid fraction, so that the velocity follows the tanh profile of the
+    density; `frame_ux` is added to every node (reference frame moving to the
+    right)."""
     x, y = _coords(nx, ny)
     cx, cy = (nx / 2.0, film + radius + 10.0) if drop_center is None else drop_center
     r = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
@@ -94,7 +96,7 @@ def splash(nx, ny, rho_g, rho_l, radius, width, *, film=40, drop_center=None, dr
     phi = np.maximum(phi_drop, phi_film)
     rho = rho_g + (rho_l - rho_g) * phi
     ux = np.full_like(rho, frame_ux)
-    uy = np.where(phi_drop > 0.5, drop_uy, 0.0)
+    uy = drop_uy * phi_drop if smooth_velocity else np.where(phi_drop > 0.5, drop_uy, 0.0)
     return np.ascontiguousarray(rho), ux, np.ascontiguousarray(uy)
 
 

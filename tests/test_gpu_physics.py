@@ -23,6 +23,8 @@ by the oracle):
   With both terms the slope matches the integral to 3 %; Eq. 10's term alone
   is about half of it.
 """
+import math
+
 import mpmath as mp
 import numpy as np
 import pytest
@@ -406,6 +408,73 @@ def test_drop_spreading_law(Re, k, W, collision, rates):
         Re, min(C), max(C), expo, np.exp(logc)), flush=True)
     assert 1.2 <= min(C) and max(C) <= 1.55
     assert 0.5 <= expo <= 0.72
+
+
+def _splash_run(Re, collision, rates, cap, steps, check=100, watch=None):
+    """The splash of _spreading (k = 0.1, 6-node interfaces) with the drop's
+    velocity following its tanh profile; returns (steps run before the
+    density went non-finite or `steps`, the largest density seen in the
+    first `watch` steps, the final density or None)."""
+    nx, ny, D, U, film, k, W = 1000, 300, 100.0, 0.1, 30, 0.1, 6.0
+    w1 = float(mp.re(A.EOS(A.EOS_PR).interface(0.6)["width1"]))
+    g, l = A.coexistence(A.EOS_PR, 0.6)
+    p = lbm.params(lbm.EOS_PR, 0.6, nx, ny, kappa=(W * k / w1) ** 2, tau=3 * U * D / Re + 0.5,
+                   k=k, mu_cap=cap, bc_y=1, collision=collision, rates=rates)
+    rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, D / 2, W, film=film,
+                                   drop_center=(nx / 2, film + D / 2 + 5.0), drop_uy=-U,
+                                   smooth_velocity=True)
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    peak, done = 0.0, 0
+    try:
+        while done < steps:
+            if watch and done < watch:
+                s.step(check)
+                peak = max(peak, float(s.moments()[0].max()))
+                done += check
+            else:
+                s.run_until_converged(0.0, check_every=check, max_steps=steps - done)
+                done = steps
+        rho = s.moments()[0]
+        # mass conservation: to round-off, which drifts by up to ~1e-16 of
+        # the mass per step (the nine equilibria sum to rho in floating point
+        # only to the last bits)
+        assert abs(rho.sum() / rho0.sum() - 1.0) < 1e-11
+    except lbm.LBMError:
+        done, rho = s.steps_taken, None
+    s.close()
+    return done, peak, rho
+
+
+def test_upper_limit_carries_the_high_reynolds_splash():
+    """Sec. 5.6 and Fig. 14: the drop of Sec. 5.5 (PR, T/Tc = 0.6, density
+    ratio 853) at Re = 400 with MRT.  On impact the liquid is compressed past
+    1/b = 10.5, where psi' of Eq. 19 has no value; with the upper limit 6 the
+    run goes on (mass conserved to round-off), the sheet thrown up from the
+    impact breaks into separate liquid pieces (secondary droplets) by
+    t* = 4.5, and the film and drop stay finite; without the limit the same
+    run goes non-finite within the first 200 steps, as the paper describes.
+    At Re = 150 the limit also carries BGK, and at Re = 400 MRT holds where
+    BGK does not (the paper's remark that MRT is the more stable).  The
+    ghost-moment rate s_q is 1.2 here: with the printed 1.9 this run goes
+    non-finite within 100 steps."""
+    mrt, bgk = lbm.COLLISION_MRT, lbm.COLLISION_BGK
+    rates = (1.64, 1.54, 1.2)
+    done, peak, rho = _splash_run(400, mrt, rates, 6.0, 4700, check=50, watch=1000)
+    print("\nRe 400 MRT, limit 6: %d steps, peak density %.3f" % (done, peak), flush=True)
+    assert done == 4700 and rho is not None
+    assert peak > 10.5
+    g, l = A.coexistence(A.EOS_PR, 0.6)
+    from scipy import ndimage
+    pieces = ndimage.label(rho > 0.5 * (g + l))[1]
+    print("liquid pieces at t* = 4.5: %d" % pieces, flush=True)
+    assert pieces >= 3
+    done_nolim = _splash_run(400, mrt, rates, math.inf, 2000)[0]
+    done_bgk = _splash_run(400, bgk, lbm.MRT_RATES, 6.0, 2000)[0]
+    print("Re 400 without the limit: non-finite after %d steps; BGK with the limit: %d" % (
+        done_nolim, done_bgk), flush=True)
+    assert done_nolim <= 300 and done_bgk <= 300
+    assert _splash_run(150, bgk, lbm.MRT_RATES, 6.0, 3000)[0] == 3000
+    assert _splash_run(150, bgk, lbm.MRT_RATES, math.inf, 2000)[0] <= 300
 
 
 def test_contact_angle_follows_the_wall_chemical_potential():
