@@ -421,6 +421,45 @@ def small_mesh_bench(torch, lbm, inputs, steps=2000):
     return out
 
 
+def large_mesh_bench(torch, lbm, inputs, steps=200):
+    """A 16384 x 8192 splash between walls (134 M nodes, ~36 GB of device
+    state): rows of 16384 nodes run every row pass over windowed segments,
+    columns of 8192 the factorised solve with 8-node chunks.  Whole-step rate
+    over `steps` steps after autotuning."""
+    nx, ny = 16384, 8192
+    c = SPLASH
+    p = lbm.params(lbm.EOS_CS, c["T_r"], nx, ny, kappa=c["kappa"], tau=c["tau"], k=c["k"],
+                   mu_cap=c["mu_cap"], bc_y=1)
+    g, l = lbm.maxwell(p)
+    rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, 4 * c["radius"], c["width"],
+                                   film=4 * c["film"], drop_uy=c["drop_uy"])
+    stream = torch.cuda.current_stream()
+    d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+    del rho0, ux0, uy0
+    s = lbm.Solver(p, *d, stream=stream.cuda_stream)
+    del d
+    s.step(10)
+    s.autotune(2)
+    s.step(10)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    kms = s.time_step_kernels(20)
+    finite = bool(torch.isfinite(torch.as_tensor(s.moments(device=True)[0])).all())
+    ws = lbm.workspace_bytes(p)
+    s.close()
+    return {"workload": "drop splashing on a 160-node film between walls, CS, 16384x8192, "
+                        "T/Tc=0.6, R=400, tau=0.6, k=0.2, kappa=0.1",
+            "nx": nx, "ny": ny, "steps": steps, "finite": finite,
+            "device_bytes": ws, "ms_per_step": round(ms, 4),
+            "MLUPS": round(nx * ny / (ms * 1e-3) / 1e6, 1),
+            "kernels_ms": {n: round(t, 4) for n, t in zip(SEG_NAMES, kms)}}
+
+
 def workload_params(lbm):
     return lbm.params(lbm.EOS_PR, CFG["T_r"], NX, NY, kappa=CFG["kappa"], tau=CFG["tau"],
                       k=CFG["k"], mu_cap=CFG["mu_cap"])
@@ -493,6 +532,9 @@ def main():
                     help="the 4096 x 2048 splash between walls: its whole-step rate and "
                          "in-sequence kernel times, the roofline point (hbm, default); also "
                          "the 10,000-step run in two frames (full, about 20 s more); or none")
+    ap.add_argument("--large", choices=["16384x8192", "none"], default="16384x8192",
+                    help="a 16384 x 8192 splash between walls, 200 steps (rows over windowed "
+                         "segments; ~36 GB of device state), or none")
     ap.add_argument("--small", choices=["64", "none"], default="64",
                     help="the 64 x 64 drop of 2000 steps, launched kernel by kernel and from "
                          "captured graphs (64, default), or none")
@@ -576,6 +618,10 @@ def main():
         splash = splash_hbm(torch, lbm, inputs, kernel_steps=args.kernel_steps)
         if args.splash == "full":
             splash["two_frames_10000_steps"] = splash_bench(torch, lbm, inputs)
+    large = None
+    if args.large != "none":
+        print("16384 x 8192 splash", file=sys.stderr, flush=True)
+        large = large_mesh_bench(torch, lbm, inputs)
     small = None
     if args.small != "none":
         print("64 x 64 drop: launches one by one and from graphs", file=sys.stderr, flush=True)
@@ -641,6 +687,7 @@ def main():
         "drop_after_run": report,
         "splash_hbm": splash,
         "small_mesh_64": small,
+        "large_mesh": large,
         "sweep": sweep,
         "warm_start": warm,
         "cpu_baseline": cpu,

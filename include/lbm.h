@@ -213,17 +213,19 @@ lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int 
 /* Autotuner: for each strip width of the column pass (columns per
  * workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS holds and, for the
  * factorised solve, each chunk length (column nodes per thread) in
- * {4, 8, 16}, then for each collision pass variant of
+ * {4, 8, 16}; for column tiles with windows (see lbm_set_column_shape) of
+ * width 4, 8 or 16 and chunk 8 or 16 where the columns are long enough; then
+ * for each collision pass variant of
  * lbm_set_collision_variant that the mesh allows, time `repeats` whole steps
  * (the three passes from the current state into the spare buffers, HIP
  * events), so that every candidate meets the caches as a real step leaves
  * them; keep the fastest of each for the context.  ms[] reports the time
  * per step.  The state f is
- * not changed.  widths[], chunks[] and ms[] (room for 17 entries each, may be
+ * not changed.  widths[], chunks[] and ms[] (room for 24 entries each, may be
  * NULL) receive the candidates and their average time in milliseconds --
- * column candidates as (width, chunk; chunk 0 = general reduction kernel),
- * collision candidates as (0, variant) -- and *count (may be NULL) their
- * number.  Synchronises. */
+ * column candidates as (width, chunk; chunk 0 = general reduction kernel,
+ * chunk < 0 = tiles of chunk -chunk), collision candidates as (0, variant)
+ * -- and *count (may be NULL) their number.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, double *ms,
                         int *count);
 
@@ -247,9 +249,14 @@ lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
 
 /* Set the column-pass shape directly (width in columns per workgroup, chunk
  * in column nodes per thread of the factorised solve, 0 for the general
- * reduction kernel).  LBM_E_INVALID if the shape does not fit one workgroup
- * or the chunk is not 0, 4, 8 or 16.  Results of every shape agree to
- * round-off. */
+ * reduction kernel).  A negative chunk (-4, -8 or -16; width 4, 8 or 16)
+ * cuts the columns into tiles of rows, one workgroup per tile, each tile
+ * taking its three chained derivatives over a window of 3 (M + 1) chunks
+ * above and below it (M the carries of the factorised solve: 11, 6, 3) --
+ * mirrored about a wall -- so that strips stay wide on long columns (the
+ * default for columns of more than 4096 nodes: width 4, chunk 8; tiles of
+ * 1712 rows); it needs columns of more than one tile.  LBM_E_INVALID if the
+ * shape does not fit.  Results of every shape agree to round-off. */
 lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
 
 /* Allocation-free stepping, for callers that cannot allocate device memory

@@ -49,7 +49,7 @@ constexpr int kMaxLine = kMaxBlockElems;  // longest line a block holds in LDS
 // longer lines: rows over windowed segments (a whole number of 4-node
 // chunks), columns on the factorised solve with 8- or 16-node chunks
 constexpr int kMaxRow = 1 << 20;
-constexpr int kMaxCol = 16384;
+constexpr int kMaxCol = 1 << 20;
 constexpr int kDefaultStripWidth = 4;     // columns per block before tuning
 constexpr int kDefaultChunk = 4;          // column nodes per thread before tuning
 
@@ -100,12 +100,11 @@ lbm_status validate(const lbm_params *p, std::string *why)
     };
     if (!p) return bad("params is NULL");
     if (p->nx < 8 || p->ny < 8 || p->nx > kMaxRow || p->ny > kMaxCol)
-        return bad("nx must lie in [8, 1048576] and ny in [8, 16384]");
+        return bad("nx and ny must lie in [8, 1048576]");
     if (p->nx > kMaxLine && p->nx % kIirRowChunk != 0)
         return bad("rows longer than 4096 nodes must be a multiple of 4");
-    if (p->ny > kMaxLine && !(p->ny % 16 == 0 || (p->ny <= 8192 && p->ny % 8 == 0)))
-        return bad("columns longer than 4096 nodes must be a multiple of 8 (up to 8192) "
-                   "or of 16");
+    if (p->ny > kMaxLine && p->ny % 8 != 0)
+        return bad("columns longer than 4096 nodes must be a multiple of 8");
     if (p->bc_y != 0 && p->bc_y != 1) return bad("bc_y must be 0 or 1");
     if (p->eos < LBM_EOS_VDW || p->eos > LBM_EOS_CS) return bad("unknown EOS");
     if (!(finite(p->a) && p->a > 0 && finite(p->b) && p->b > 0 && finite(p->R) && p->R > 0))
@@ -212,11 +211,9 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     set_row_shape(&k);
     k.row_keep = 1;
     set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
-    // columns longer than one workgroup's reduction holds: the factorised
-    // solve with the shortest chunk that fits
-    for (int lc : {8, 16})
-        if (!k.use_iir_cols && k.ny > kMaxLine) set_col_shape(&k, 1, lc);
-    if (!k.use_iir_cols && k.ny > kMaxLine) {
+    // columns longer than one workgroup's reduction holds: tiles with
+    // windows, 4 columns wide
+    if (k.ny > kMaxLine && !set_col_tiles(&k, kDefaultStripWidth, 8)) {
         *why = "no column solve holds columns of this length";
         return false;
     }
@@ -799,7 +796,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     };
     const int cand_w[] = {1, 2, 4, 8, 16};
     const int cand_c[] = {4, 8, 16};
-    int n = 0, best_w = c->kp.cols_per_block, best_c = c->kp.col_lc;
+    // best_c < 0: tiles with windows of chunk -best_c
+    int n = 0, best_w = c->kp.cols_per_block, best_c = c->kp.col_win ? -c->kp.col_lc : c->kp.col_lc;
     double best = INFINITY;
     hipError_t err = hipSuccess;
     for (int cw = 0; cw < 15 && err == hipSuccess; ++cw) {
@@ -822,7 +820,30 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
             best_c = ch;
         }
     }
-    if (err == hipSuccess) set_col_shape(&c->kp, best_w, best_c);
+    // column tiles with windows (reported with the chunk negated)
+    const int tile_w[] = {4, 8, 16}, tile_c[] = {8, 16};
+    for (int cw = 0; cw < 6 && err == hipSuccess; ++cw) {
+        const int w = tile_w[cw / 2], ch = tile_c[cw % 2];
+        KParams kp = c->kp;
+        if (!set_col_tiles(&kp, w, ch)) continue;
+        double avg = 0.0;
+        if ((err = steps_ms(kp, &avg)) != hipSuccess) break;
+        if (widths) widths[n] = w;
+        if (chunks) chunks[n] = -ch;
+        if (ms) ms[n] = avg;
+        ++n;
+        if (avg < best) {
+            best = avg;
+            best_w = w;
+            best_c = -ch;
+        }
+    }
+    if (err == hipSuccess) {
+        if (best_c < 0)
+            (void)set_col_tiles(&c->kp, best_w, -best_c);
+        else
+            set_col_shape(&c->kp, best_w, best_c);
+    }
     // collision pass: populations held in registers or read twice, in one
     // pass or split for long rows
     double best_row = INFINITY;
@@ -867,8 +888,16 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
 {
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
+    if (chunk < 0) {
+        KParams kp = c->kp;
+        if (!set_col_tiles(&kp, width, -chunk))
+            return fail(c, LBM_E_INVALID, "these column tiles do not fit this mesh");
+        c->kp = kp;
+        drop_graphs(c);
+        return LBM_OK;
+    }
     if (chunk != 0 && chunk != 4 && chunk != 8 && chunk != 16)
-        return fail(c, LBM_E_INVALID, "chunk must be 0, 4, 8 or 16");
+        return fail(c, LBM_E_INVALID, "chunk must be 0, 4, 8, 16 or negated for tiles");
     KParams kp = c->kp;
     set_col_shape(&kp, width, chunk == 0 ? 4 : chunk);
     if (kp.cols_per_block != width) return fail(c, LBM_E_INVALID, "width does not fit a workgroup");

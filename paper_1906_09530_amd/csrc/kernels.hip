@@ -486,6 +486,8 @@ void set_row_shape(KParams *p)
 
 void set_col_shape(KParams *p, int width, int chunk)
 {
+    p->col_win = 0;
+    p->col_tile = 0;
     p->col_lc = chunk;
     iir_carry(*p, chunk, &p->iir_m_col, &p->iir_qL_col);
     // the factorised solve holds up to kMaxColElems nodes of a strip (one
@@ -508,6 +510,32 @@ void set_col_shape(KParams *p, int width, int chunk)
     p->col_threads = round_threads(w * p->ny);
     const int nb = col_blocks(*p);
     p->col_xcd_groups = (nb % 8 == 0 && nb >= 64 && p->nx % w == 0) ? 8 : 1;
+}
+
+bool set_col_tiles(KParams *p, int width, int chunk)
+{
+    if (!(width == 4 || width == 8 || width == 16) || !(chunk == 4 || chunk == 8 || chunk == 16))
+        return false;
+    const int hc = col_tile_chunks(width, chunk), E = col_window_chunks(chunk);
+    int M = 0;
+    double qL = 0.0;
+    iir_carry(*p, chunk, &M, &qL);
+    // tiles of at least 8 chunks; the window reaches past one wall only, and
+    // more than one tile per column
+    if (hc < 8 || p->ny % chunk != 0 || p->ny < 2 * E * chunk || p->ny <= hc * chunk ||
+        M > (chunk == 4 ? 11 : (chunk == 8 ? 6 : 3)))
+        return false;
+    p->col_lc = chunk;
+    p->iir_m_col = M;
+    p->iir_qL_col = qL;
+    p->use_iir_cols = 1;
+    p->col_win = 1;
+    p->col_tile = hc * chunk;
+    p->cols_per_block = width;
+    p->col_threads = (width * (hc + 2 * E) + 63) / 64 * 64;
+    const int nb = ((p->nx + width - 1) / width) * ((p->ny + p->col_tile - 1) / p->col_tile);
+    p->col_xcd_groups = (nb % 8 == 0 && nb >= 64) ? 8 : 1;
+    return true;
 }
 
 static size_t row_lds(const KParams &p) { return 2 * sizeof(double) * p.rows_per_block * p.nx; }

@@ -42,6 +42,9 @@ struct KParams {
     // pole q, 1/q, K = 1/(1 + 2 al q), powers q^0..q^16, and per pass the
     // chunk length, its power q^LC and the number of carried chunks M
     int use_iir_rows, use_iir_cols, col_lc;
+    // column pass over tiles of col_tile rows with windows (col_win; tall
+    // columns), else over whole columns
+    int col_win, col_tile;
     int row_keep;   // collision pass holds f in registers (tuned)
     int row_split;  // collision pass over row segments (tuned; see below)
     int row_win;    // rows beyond one workgroup: every row pass over segments
@@ -106,6 +109,15 @@ int rho_delta_blocks(const KParams &p);
 // the factorised-inverse kernels whenever the line allows it.
 void set_row_shape(KParams *p);
 void set_col_shape(KParams *p, int width, int chunk);
+// The column pass over tiles: strips of `width` columns (4, 8 or 16) cut into
+// tiles of rows, chunk 4, 8 or 16, each tile with a window above and below.
+// False (p unchanged) if the columns are too short for a tile's windows or
+// not a whole number of chunks.
+bool set_col_tiles(KParams *p, int width, int chunk);
+// Rows of one tile (in chunks) for a strip width and chunk length, and the
+// window's chunks on each side.
+int col_tile_chunks(int width, int lc);
+int col_window_chunks(int lc);
 
 // ---- batches of independent meshes ------------------------------------
 // Device-side buffers of one mesh of a batch.

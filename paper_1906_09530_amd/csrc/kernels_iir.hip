@@ -201,40 +201,45 @@ __device__ __forceinline__ void iir_solve(const KParams &p, const Chunk<LC> &m, 
 }
 
 // The same solve on a window of nw consecutive chunks w = 0 .. nw - 1 of a
-// row, which the caller loads with x taken periodically: every chunk
-// publishes its edge values and (w in [1, nw - 1)) its carries, and the
-// chunks w in [MC + 1, nw - MC - 1) receive the derivative.  Those chunks sum
-// the carries of exactly the MC chunks on each side that the whole-row solve
-// sums, computed from the same values, so their derivative is bitwise the
-// whole-row one.  The whole block calls it together.
+// line, which the caller loads (x periodic; a column periodic or mirrored
+// about its walls): every chunk publishes its edge values and (w in
+// [1, nw - 1)) its carries, and the chunks w in [MC + 1, nw - MC - 1) receive
+// the derivative.  Those chunks sum the carries of exactly the MC chunks on
+// each side that the whole-line solve sums, computed from the same values,
+// so their derivative is the whole-line one (bitwise for rows).  The block
+// holds nl such windows side by side (line l of them, interleaved in LDS so
+// that neighbouring lines sit in neighbouring banks); the whole block calls
+// it together.
 template <int LC>
 __device__ __forceinline__ void iir_solve_window(const KParams &p, int w, int nw, double qL,
                                                  const double (&u)[LC], double *vbuf, double *cP,
-                                                 double *cB, double (&d)[LC])
+                                                 double *cB, double (&d)[LC], int l = 0,
+                                                 int nl = 1)
 {
     constexpr int MC = kCarry(LC);
+    auto E = [&](int ci, int e) { return (4 * ci + e) * nl + l; };
     if (w < nw) {
-        vbuf[4 * w + 0] = u[0];
-        vbuf[4 * w + 1] = u[1];
-        vbuf[4 * w + 2] = u[LC - 2];
-        vbuf[4 * w + 3] = u[LC - 1];
+        vbuf[E(w, 0)] = u[0];
+        vbuf[E(w, 1)] = u[1];
+        vbuf[E(w, 2)] = u[LC - 2];
+        vbuf[E(w, 3)] = u[LC - 1];
     }
     __syncthreads();
     double y[LC], z[LC];
     if (w >= 1 && w < nw - 1) {
         double Pc, Bc;
-        iir_chunk<LC>(p, u, vbuf[4 * (w - 1) + 2], vbuf[4 * (w - 1) + 3], vbuf[4 * (w + 1)],
-                      vbuf[4 * (w + 1) + 1], y, z, Pc, Bc);
-        cP[w] = Pc;
-        cB[w] = Bc;
+        iir_chunk<LC>(p, u, vbuf[E(w - 1, 2)], vbuf[E(w - 1, 3)], vbuf[E(w + 1, 0)],
+                      vbuf[E(w + 1, 1)], y, z, Pc, Bc);
+        cP[w * nl + l] = Pc;
+        cB[w * nl + l] = Bc;
     }
     __syncthreads();
     if (w < MC + 1 || w >= nw - MC - 1) return;
     double Yc = 0.0, Zc = 0.0;
 #pragma unroll
     for (int mm = MC; mm >= 1; --mm) {
-        Yc = Yc * qL + cP[w - mm];
-        Zc = Zc * qL + cB[w + mm];
+        Yc = Yc * qL + cP[(w - mm) * nl + l];
+        Zc = Zc * qL + cB[(w + mm) * nl + l];
     }
     iir_combine<LC>(p, Yc, Zc, y, z, d);
 }
@@ -480,6 +485,113 @@ __global__ __launch_bounds__(MAXT) void k_cols_mu_iir(KParams p, const double *_
                                                       double *__restrict__ fy_out)
 {
     cols_mu_body<LC>(p, strip_of_block(p) * p.cols_per_block, rho, mux, mu_out, fy_out);
+}
+
+// Pass B over a tile of col_tile rows of columns [x0, x0 + cols_per_block),
+// with a window of kColWin chunks above and below it: each of the three
+// chained derivatives needs MC + 1 chunks of the previous one's values past
+// the chunks it serves, so the window holds three times that, and the tile's
+// derivatives are the whole-column values to round-off.  Beyond a wall the
+// window holds the column's mirror image: rho and the row part of mu are
+// even about the wall, so their derivatives come out odd and even as the
+// whole-column solve's ghost chunks make them, and for wetting walls
+// mu - mu_wall is odd (its sign flips beyond the wall).  Columns of any
+// length run in tiles of one width.
+template <int LC>
+constexpr int kColWin = 3 * (kCarry(LC) + 1);
+
+template <int LC>
+__device__ __forceinline__ void cols_mu_win_body(const KParams &p, int x0, int ty,
+                                                 const double *__restrict__ rho,
+                                                 const double *__restrict__ mux,
+                                                 double *__restrict__ mu_out,
+                                                 double *__restrict__ fy_out)
+{
+    constexpr int E = kColWin<LC>;
+    extern __shared__ double smem[];
+    const int nx = p.nx, ny = p.ny, W = p.cols_per_block;
+    const int y0 = ty * p.col_tile, hc = min(p.col_tile, ny - y0) / LC, nw = hc + 2 * E;
+    const int w = threadIdx.x / W, l = threadIdx.x - w * W, c = w - E;
+    const int col = x0 + l;
+    const bool in = w < nw && col < nx;
+    const bool core = in && c >= 0 && c < hc;
+    // the chunk's rows; chunks never straddle a wall (ny and the tiles are
+    // whole chunks)
+    const int yc = y0 + c * LC;
+    const bool beyond = p.bc_y && (yc < 0 || yc >= ny);
+    auto row_of = [&](int y) -> size_t {
+        if (p.bc_y) y = y < 0 ? -1 - y : (y >= ny ? 2 * ny - 1 - y : y);
+        else y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+        return (size_t)y * nx + col;
+    };
+    double *vbuf = smem, *cP = smem + 4 * nw * W, *cB = cP + nw * W;
+    double r[LC], mx[LC];
+    if (in) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            const size_t node = row_of(yc + k);
+            r[k] = rho[node];
+            mx[k] = mux[node];
+        }
+    }
+    const double qL = p.iir_qL_col;
+    if (p.sc) {
+        // pseudopotential model: F_y = c_s^2 psi d/dy psi; psi (even about
+        // a wall) is passed on in the mu plane
+        double dps[LC];
+        iir_solve_window<LC>(p, w, nw, qL, mx, vbuf, cP, cB, dps, l, W);
+        if (core) {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                const size_t node = (size_t)(yc + k) * nx + col;
+                mu_out[node] = mx[k];
+                fy_out[node] = CS2 * mx[k] * dps[k];
+            }
+        }
+        return;
+    }
+    double dyr[LC], dyy[LC], mu[LC], dym[LC];
+#pragma unroll
+    for (int k = 0; k < LC; ++k) dyr[k] = dyy[k] = 0.0;
+    iir_solve_window<LC>(p, w, nw, qL, r, vbuf, cP, cB, dyr, l, W);
+    if (!p.kappa_zero) iir_solve_window<LC>(p, w, nw, qL, dyr, vbuf, cP, cB, dyy, l, W);
+#pragma unroll
+    for (int k = 0; k < LC; ++k) {
+        double v = mx[k];
+        if (!p.kappa_zero) v -= p.kappa * dyy[k];
+        mu[k] = v;
+    }
+    if (p.wet) {
+        double mw[LC];
+        const double sg = beyond ? -1.0 : 1.0;
+#pragma unroll
+        for (int k = 0; k < LC; ++k) mw[k] = sg * (mu[k] - p.mu_wall);
+        iir_solve_window<LC>(p, w, nw, qL, mw, vbuf, cP, cB, dym, l, W);
+    } else {
+        iir_solve_window<LC>(p, w, nw, qL, mu, vbuf, cP, cB, dym, l, W);
+    }
+    if (core) {
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            const size_t node = (size_t)(yc + k) * nx + col;
+            mu_out[node] = mu[k];
+            fy_out[node] = -r[k] * dym[k] + CS2 * dyr[k];
+        }
+    }
+}
+
+// One workgroup per (strip, tile); the permuted block index keeps the tiles
+// of one strip, and neighbouring strips, on one XCD.
+template <int LC>
+__global__ __launch_bounds__(1024) void k_cols_mu_win(KParams p, const double *__restrict__ rho,
+                                                      const double *__restrict__ mux,
+                                                      double *__restrict__ mu_out,
+                                                      double *__restrict__ fy_out)
+{
+    const int nt = (p.ny + p.col_tile - 1) / p.col_tile;
+    const int idx = strip_of_block(p), strip = idx / nt;
+    cols_mu_win_body<LC>(p, strip * p.cols_per_block, idx - strip * nt, rho, mux, mu_out,
+                         fy_out);
 }
 
 // Pass C on rows [y0, y0 + rows_per_block) of one mesh.
@@ -1089,9 +1201,34 @@ hipError_t launch_rows_rho_iir(const KParams &p, const double *g, double *rho, d
     return hipGetLastError();
 }
 
+int col_tile_chunks(int width, int lc)
+{
+    const int E = lc == 4 ? kColWin<4> : (lc == 8 ? kColWin<8> : kColWin<16>);
+    return kMaxBlockThreads / width - 2 * E;
+}
+
+int col_window_chunks(int lc)
+{
+    return lc == 4 ? kColWin<4> : (lc == 8 ? kColWin<8> : kColWin<16>);
+}
+
 hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
                               double *fy, hipStream_t s)
 {
+    if (p.col_win) {
+        const int W = p.cols_per_block, nw = p.col_tile / p.col_lc + 2 * col_window_chunks(p.col_lc);
+        const int nb = ((p.nx + W - 1) / W) * ((p.ny + p.col_tile - 1) / p.col_tile);
+        const size_t lds = sizeof(double) * 6 * (size_t)nw * W;
+        const int T = (W * nw + 63) / 64 * 64;
+#define ARGS dim3(nb), dim3(T), lds, s, p, rho, mux, mu, fy
+        switch (p.col_lc) {
+        case 4: hipLaunchKernelGGL(k_cols_mu_win<4>, ARGS); break;
+        case 8: hipLaunchKernelGGL(k_cols_mu_win<8>, ARGS); break;
+        default: hipLaunchKernelGGL(k_cols_mu_win<16>, ARGS); break;
+        }
+#undef ARGS
+        return hipGetLastError();
+    }
     const int T = col_threads_iir(p);
 #define ARGS dim3(col_blocks(p)), dim3(T), col_lds_iir(p), s, p, rho, mux, mu, fy
     switch (p.col_lc) {

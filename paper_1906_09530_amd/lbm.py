@@ -284,8 +284,9 @@ class Solver:
         return list(ms)[:cnt.value]
 
     def autotune(self, repeats=20):
-        """Pick the fastest column-pass shape; returns {(width, chunk): ms}
-        (chunk 0: the general reduction kernel)."""
+        """Pick the fastest column-pass shape and collision variant; returns
+        {(width, chunk): ms} (chunk 0: the general reduction kernel; chunk < 0:
+        tiles with windows; (0, v): collision variant v)."""
         w = (C.c_int * 24)()
         ch = (C.c_int * 24)()
         ms = (C.c_double * 24)()
@@ -294,12 +295,14 @@ class Solver:
         return {(w[i], ch[i]): ms[i] for i in range(n.value)}
 
     def set_collision_variant(self, variant):
-        """0: one pass reading f twice; 1: one pass, f in registers; 2: split
-        for rows of more than 1024 nodes (derivative pass + collision over
-        equal row segments of at most 1024 nodes)."""
+        """0: one pass reading f twice; 1: one pass, f in registers; 2: over
+        896-node row segments with derivative windows (rows of more than 896
+        nodes; the only variant beyond 4096)."""
         _check(load().lbm_set_collision_variant(self.ctx, int(variant)), self.ctx)
 
     def set_column_shape(self, width, chunk):
+        """Strip width and chunk of the column pass (chunk 0: general
+        reduction kernel; negative: tiles with windows)."""
         _check(load().lbm_set_column_shape(self.ctx, int(width), int(chunk)), self.ctx)
 
     def get_state(self, device=False):

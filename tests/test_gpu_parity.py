@@ -574,14 +574,18 @@ def test_rows_longer_than_a_workgroup(nx, ny, walls):
     """Rows beyond 4096 nodes run every row pass over segments with windows
     (collision and observation: 896-node segments, 5000 = 5 x 896 + 520;
     pass A: 832-node segments, 5000 = 6 x 832 + 8, a last segment of two
-    chunks): parity with the oracle after 60 and 120 steps, the observation
+    chunks), here with a drop across the periodic seam x = 0 that the first
+    and last segments' windows wrap over: parity with the oracle after 60
+    and 120 steps, the observation
     pass (mu, F of Eqs. 12 and 33) at the start, and a resumed run ends
     bitwise where the uninterrupted one does."""
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0,
                          bc_y=walls, wall_ux=0.01 if walls else 0.0)
     g, l = A.coexistence(p.eos, p.T_r)
+    # a drop across the periodic seam x = 0 (rolled from the row's middle)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, ny / 3.0, 3.0, seed=31, noise=1e-4,
-                                    center=(nx - 20.5, ny / 2.0))
+                                    center=(nx / 2 + 6.5, ny / 2.0))
+    rho0 = np.ascontiguousarray(np.roll(rho0, nx // 2, axis=1))
     s = lbm.Solver(p, rho0, ux0, uy0)
     mu, fx, fy = s.force_fields()
     f = oracle.init(op, rho0, ux0, uy0)
@@ -620,3 +624,45 @@ def test_columns_longer_than_a_workgroup_reduction(nx, ny, walls):
     g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 3.0, seed=5, noise=1e-4)
     _run_case("longcols%dx%d" % (nx, ny), p, op, rho0, ux0, uy0, [40])
+
+
+@pytest.mark.parametrize("case", ["periodic", "walls_wetting", "pseudopotential", "kappa0_walls"])
+def test_column_tiles_match_oracle(case):
+    """The column pass over tiles of rows with windows (lbm_set_column_shape
+    with a negative chunk): periodic columns (4 wide, 8-node chunks: tiles of
+    1712, 1712 and 672 rows), between wetting walls (8 wide, 16-node chunks:
+    1664, 1664 and 272, the windows mirrored about the walls with mu - mu_wall
+    odd), the pseudopotential model (16 wide: 176-row tiles), and kappa = 0
+    between walls (8 wide: 688-row tiles; one derivative before mu).  Parity with the oracle after 40
+    steps, and the whole-column shape agrees to round-off."""
+    if case == "periodic":
+        nx, ny, kw, shape = 32, 4096, dict(), (4, -8)
+    elif case == "walls_wetting":
+        nx, ny, kw, shape = 24, 3600, dict(bc_y=1, wetting=1, mu_wall=-0.05), (8, -16)
+    elif case == "pseudopotential":
+        nx, ny, kw, shape = 16, 2400, dict(force=lbm.FORCE_SC), (16, -8)
+    else:
+        nx, ny, kw, shape = 20, 2048, dict(bc_y=1), (8, -8)
+    kappa = 0.0 if case == "kappa0_walls" else 0.1
+    p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=kappa, tau=0.8, k=0.2, mu_cap=6.0,
+                         **kw)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 3.0, seed=7, noise=1e-4)
+    # interfaces a few nodes from a tile edge and, between walls, the liquid
+    # against the bottom wall
+    rho0 = np.ascontiguousarray(np.roll(rho0, ny // 4 - 3, axis=0))
+    print("\n[case] column tiles %s %dx%d shape %s" % (case, nx, ny, shape), flush=True)
+    ref = _oracle_after(op, rho0, ux0, uy0, [40])
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    s.set_column_shape(*shape)
+    s.step(40)
+    er, ev = _errors(s.moments(), ref[40])
+    print("  rel err rho %.2e, v %.2e" % (er, ev), flush=True)
+    assert er <= TOL and ev <= TOL
+    b = lbm.Solver(p, rho0, ux0, uy0)
+    b.set_column_shape(1, 16)                     # whole columns
+    b.step(40)
+    er2, ev2 = _errors(s.moments(), b.moments())
+    assert er2 <= 1e-12 and ev2 <= 1e-10
+    s.close()
+    b.close()

@@ -71,7 +71,7 @@ def _init_status(p, rho):
 
 @pytest.mark.parametrize("field,value", [("tau", 0.5), ("tau", 0.3), ("k", 0.0), ("kappa", -1.0),
                                           ("nx", 7), ("ny", 5001), ("nx", 4098),
-                                          ("ny", 8200), ("ny", 16400), ("nx", 1 << 21),
+                                          ("ny", 8204), ("ny", 1 << 21), ("nx", 1 << 21),
                                           ("cfd_alpha", 0.3),
                                           ("bc_y", 2), ("eos", 9), ("mu_cap", math.nan),
                                           ("T_r", -0.1), ("wall_ux", math.inf)])
@@ -154,10 +154,11 @@ def test_eos_values_match_oracle(eos, T_r):
 
 
 @pytest.mark.parametrize("nx,ny", [(4100, 16), (5000, 32), (1 << 20, 8), (16, 5000), (24, 8192),
-                                   (16, 9216), (32, 16384), (8192, 8192)])
+                                   (16, 9216), (32, 16384), (8192, 8192), (8, 40000),
+                                   (8, 1 << 20)])
 def test_long_lines_are_accepted(nx, ny):
     """Rows beyond 4096 nodes (a multiple of 4, over windowed segments) and
-    columns beyond 4096 (multiples of 8 up to 8192, of 16 up to 16384, on the
-    factorised solve) size a workspace."""
+    columns beyond 4096 (a multiple of 8, over tiles of rows with windows)
+    size a workspace."""
     p = lbm.params(4, 0.7, nx, ny, kappa=0.1, tau=1.0, k=0.2, bc_y=1)
     assert lbm.workspace_bytes(p) >= 9 * 2 * 8 * nx * ny

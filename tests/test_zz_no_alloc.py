@@ -68,3 +68,15 @@ def test_noalloc_rejects_meshes_beyond_its_limit():
         lbm.step_noalloc(p, f, 1)
     assert ei.value.status == lbm.LBM_E_INVALID
     assert "at most" in lbm.load().lbm_last_error(None).decode()
+
+
+def test_noalloc_rows_beyond_a_workgroup_at_its_limit():
+    """A mesh of exactly the limit whose 8192-node rows run over windowed
+    segments (pass A, the collision): the same state as a context."""
+    p = lbm.params(lbm.EOS_CS, 0.7, 8192, 32, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0, bc_y=1)
+    assert p.nx * p.ny == lbm.NOALLOC_MAX_NODES
+    g, l = A.coexistence(lbm.EOS_CS, 0.7)
+    # a drop centred on the periodic seam x = 0 (rolled by half the row)
+    rho, _, _ = inputs.droplet(8192, 32, g, l, 10.0, 3.0, seed=33, noise=1e-4,
+                               center=(4096.0, 16.0))
+    _compare("cs8192x32walls", p, np.ascontiguousarray(np.roll(rho, 4096, axis=1)), 11)
