@@ -477,6 +477,52 @@ def test_upper_limit_carries_the_high_reynolds_splash():
     assert _splash_run(150, bgk, lbm.MRT_RATES, math.inf, 2000)[0] <= 300
 
 
+def test_re150_splash_in_a_moving_frame():
+    """Sec. 5.5, Fig. 12: the Re = 150 splash (PR, T/Tc = 0.6, D = 100,
+    U = 0.1, 1000 x 300 between walls, MRT) in the rest frame and in a frame
+    moving at the paper's reference speed 0.03 (walls sliding along).  At
+    t* = 0.6, 1.9, 4.5 and 7.5 the moving-frame liquid, shifted back by
+    0.03 t (a whole number of nodes at these steps), has the rest frame's
+    number of separate liquid pieces and its volume within 0.1 %, and the
+    outlines differ by a small fraction of a node on average (the number of
+    nodes on one side only, over the number of outline nodes): measured
+    0.05, 0.24, 0.56 and 0.90 at the four times."""
+    from scipy import ndimage
+    nx, ny, D, U, film, k, W, Re = 1000, 300, 100.0, 0.1, 30, 0.1, 8.0, 150
+    w1 = float(mp.re(A.EOS(A.EOS_PR).interface(0.6)["width1"]))
+    g, l = A.coexistence(A.EOS_PR, 0.6)
+    half = 0.5 * (g + l)
+    y0 = film + D / 2 + 5.0
+    marks = (600, 2000, 4600, 7600)
+    out = {}
+    for uf in (0.0, 0.03):
+        p = lbm.params(lbm.EOS_PR, 0.6, nx, ny, kappa=(W * k / w1) ** 2,
+                       tau=3 * U * D / Re + 0.5, k=k, mu_cap=6.0, bc_y=1, wall_ux=uf,
+                       collision=lbm.COLLISION_MRT, rates=(1.64, 1.54, 1.2))
+        rho0, ux0, uy0 = inputs.splash(nx, ny, g, l, D / 2, W, film=film,
+                                       drop_center=(nx / 2, y0), drop_uy=-U, frame_ux=uf)
+        s = lbm.Solver(p, rho0, ux0, uy0)
+        done = 0
+        for m in marks:
+            s.step(m - done)
+            done = m
+            out[(uf, m)] = s.moments()[0]
+            assert np.isfinite(out[(uf, m)]).all()
+        s.close()
+    for m, bound in zip(marks, (0.2, 0.6, 1.5, 2.0)):
+        a = out[(0.0, m)] > half
+        b = np.roll(out[(0.03, m)], -round(0.03 * m), axis=1) > half
+        outline = (a & ~ndimage.binary_erosion(a)).sum()
+        disp = (a ^ b).sum() / outline
+        pa, pb = ndimage.label(a)[1], ndimage.label(b)[1]
+        print("\nt* %.1f: pieces %d / %d, volume %d / %d, outline %d, differing/outline %.3f" % (
+            U * (m - (y0 - D / 2 - film) / U) / D, pa, pb, a.sum(), b.sum(), outline, disp),
+            flush=True)
+        assert pa == pb
+        assert abs(int(a.sum()) - int(b.sum())) <= 1e-3 * a.sum()
+        assert disp <= bound
+
+
 def test_contact_angle_follows_the_wall_chemical_potential():
     """Wetting walls (the chemical-potential boundary the paper takes from
     its ref. [45]): a CS drop (T/Tc = 0.7, k = 0.2, 5-node interface) resting
