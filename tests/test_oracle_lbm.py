@@ -332,3 +332,35 @@ def test_wetting_walls_conserve_mass_and_use_the_wall_value():
         r = oracle.moments(p, f)[0]
         base.append(r[0].sum())
     assert base[0] > base[1]
+
+
+def test_interface_width_scales_as_one_over_k():
+    """Sec. 5.2 (Figs. 6-7): at a fixed mesh gradient coefficient kappa the
+    interface of a converged flat slab spans 1/k times more nodes as k falls,
+    so that width * k, its width in momentum space, tends to one value.
+    Measured on the oracle (CS, T_r = 0.8, kappa = 0.1; width = (rho_l -
+    rho_g) / max |d rho / dy|): 2.41, 2.30, 2.27 at k = 0.4, 0.2, 0.1 --
+    each step in k moves it less (the discretisation error of a 3.4-node
+    interface at k = 0.4 fading), and it sits 1.66 times above the continuum
+    w1 sqrt(kappa) of Eq. 23, by the lattice's own momentum flux across the
+    interface."""
+    e = A.EOS(A.EOS_CS)
+    T_r, kap = 0.8, 0.1
+    it = e.interface(T_r)
+    g, l = float(it["rho_g"]), float(it["rho_l"])
+    w1 = float(mp.re(it["width1"]))
+    wk = []
+    for k in (0.4, 0.2, 0.1):
+        W = w1 * np.sqrt(kap) / k
+        ny = int(max(64, 16 * W)) // 4 * 4
+        p = A.params(A.EOS_CS, T_r, 4, ny, kappa=kap, tau=1.0, k=k)
+        rho, ux, uy = inputs.slab(4, ny, g, l, W)
+        f = oracle.init(p, rho, ux, uy)
+        st, steps, d = oracle.run_until_converged(p, f, 1e-12, 100, 500000)
+        assert st == 0
+        r = oracle.moments(p, f)[0][:, 0]
+        wk.append((l - g) / np.abs(np.gradient(r)).max() * k)
+    d1, d2 = wk[0] - wk[1], wk[1] - wk[2]
+    assert d1 > 0 and d2 > 0 and d2 < d1 / 3
+    assert d2 < 0.01 * wk[2]
+    assert 1.5 < wk[2] / (w1 * np.sqrt(kap)) < 1.8
