@@ -73,9 +73,8 @@ typedef enum {
 } lbm_eos;
 
 typedef struct {
-    int32_t nx, ny;     /* mesh nodes; 8 <= nx, ny <= 4096, or longer lines:
-                           nx up to 2^20 as a multiple of 4, ny up to 8192 as a
-                           multiple of 8 or up to 16384 as a multiple of 16 */
+    int32_t nx, ny;     /* mesh nodes; 8 <= nx, ny <= 2^20; lines longer than
+                           4096 nodes: nx a multiple of 4, ny a multiple of 8 */
     int32_t bc_y;       /* 0: periodic in y; 1: bounce-back walls in y */
     int32_t eos;        /* lbm_eos */
     double a, b, R;     /* EOS constants in momentum space (Sec. 3.2) */
