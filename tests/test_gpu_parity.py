@@ -565,6 +565,9 @@ def test_graph_replay_matches_launches(case):
     assert ra[1] == rb[1] == 60 and ra[2] == rb[2]
     np.testing.assert_array_equal(b.get_state(), a.get_state())
     assert a.steps_taken == b.steps_taken == 162
+    for bad in (-1, 100001):
+        with pytest.raises(lbm.LBMError):
+            b.set_graph_steps(bad)
     a.close()
     b.close()
 
