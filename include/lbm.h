@@ -265,7 +265,7 @@ lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
  * kernels, pass shapes and results as lbm_init + lbm_step on a new context
  * (no autotuning).  Every intermediate (the spare distribution buffer, the
  * density groups, the scalar planes) lives in a static device array of
- * 40 MiB that the library holds on each GPU it runs on until the process
+ * 38 MiB that the library holds on each GPU it runs on until the process
  * ends: the call allocates nothing.  Meshes of at most
  * LBM_NOALLOC_MAX_NODES nodes; larger ones return LBM_E_INVALID before any
  * work is enqueued.  The work is enqueued on hip_stream (NULL: the default
