@@ -156,6 +156,54 @@ def test_drops_follow_laplaces_law(T_r):
     assert 1.3 < jump_r.mean() / sigma < 2.0
 
 
+@pytest.mark.parametrize("eos,k", [(lbm.EOS_PR, 0.2), (lbm.EOS_RKS, 0.2), (lbm.EOS_VDW, 0.1)])
+def test_laplaces_law_for_the_other_equations_of_state(eos, k):
+    """Sec. 5.3 (Fig. 8): Laplace's law for the other EOS the paper tests, at
+    T/Tc = 0.8, 8-node interfaces (k = 0.2; VdW at k = 0.1, where its drops
+    stay finite), drops of R = 32 ... 96 converged as one batch: the
+    pressure jump k^2 [p0(rho_in) - p0(rho_out)] times the equimolar radius
+    is the same for every drop to 3 %, smaller drops carry larger jumps, and
+    the slope of the jump against 1/R equals the surface tension of the
+    integral method (Eq. 10's term plus the lattice's F^2/(4 rho), as for the
+    CS drops) to 3 %: measured slope / integral 0.999 (PR), 1.000 (RKS),
+    1.013 (VdW)."""
+    T_r = 0.8
+    e = A.EOS(eos)
+    it = e.interface(T_r)
+    T, al = it["T"], it["alpha"]
+    kappa = (W * k / float(mp.re(it["width1"]))) ** 2
+    g, l = A.coexistence(eos, T_r)
+    radii = (32, 48, 64, 96)
+    ps, r0 = [], []
+    for R in radii:
+        n = int(8 * ((2 * R + 12 * W) // 8 + 1))
+        ps.append(lbm.params(eos, T_r, n, n, kappa=kappa, tau=1.0, k=k))
+        r0.append(inputs.droplet(n, n, g, l, R, W)[0])
+    b = lbm.Batch(ps, r0)
+    _converge(b, len(radii))
+    inv_r, dp, sig = [], [], []
+    for i, p in enumerate(ps):
+        r = b.moments(i)[0]
+        n = p.nx
+        rin, rout = r[n // 2, n // 2], r[0, 0]
+        req = float(np.sqrt((r - rout).sum() / (np.pi * (rin - rout))))
+        inv_r.append(1.0 / req)
+        dp.append(k * k * float(mp.re(e.p0(mp.mpf(rin), T, al) - e.p0(mp.mpf(rout), T, al))))
+        op = A.params(eos, T_r, n, n, kappa=kappa, tau=1.0, k=k)
+        a, bb = _integral_sigma(p, op, b.get_state(i), r)
+        sig.append(a + bb)
+    jump_r = np.array(dp) / np.array(inv_r)
+    slope = float(np.polyfit(inv_r, dp, 1)[0])
+    s_int = float(np.mean(sig))
+    sigma = k * kappa ** 0.5 * float(mp.re(it["sigma1"]))
+    print("\nEOS %d: dP R = %s; slope %.4e, integral sigma %.4e (ratio %.3f), continuum %.4e" % (
+        eos, " ".join("%.4e" % v for v in jump_r), slope, s_int, slope / s_int, sigma),
+        flush=True)
+    assert np.all(np.diff(dp) < 0)
+    assert (jump_r.max() - jump_r.min()) <= 0.03 * jump_r.mean()
+    assert abs(slope / s_int - 1) <= 0.03
+
+
 # (EOS, T/Tc) of the superlarge-ratio slabs (Sec. 5.1, Fig. 4: k = 0.1)
 RATIO_SLABS = [(lbm.EOS_PR, 0.25), (lbm.EOS_RKS, 0.25), (lbm.EOS_CS, 0.20), (lbm.EOS_CS, 0.17)]
 
