@@ -287,9 +287,10 @@ lbm_status lbm_step_noalloc(const lbm_params *p, double *f, int64_t nsteps, void
  * themselves set the step time, and one graph launch replaces 3 x steps of
  * them.  Two graphs (one per starting buffer) are captured on first use, on
  * a stream the context creates, and captured again after the autotuner or
- * the collision or column settings change the pass shapes.  0 (the
- * default) launches every kernel separately.  LBM_E_INVALID for steps
- * outside [0, 100000]. */
+ * the collision or column settings change the pass shapes.  0 launches
+ * every kernel separately.  Default: 100 for meshes of at most 512 x 512
+ * nodes, 0 for larger ones (whose kernels hide the launches).
+ * LBM_E_INVALID for steps outside [0, 100000]. */
 lbm_status lbm_set_graph_steps(lbm_ctx *ctx, int64_t steps);
 
 /* Steps taken since lbm_init. */

@@ -52,6 +52,8 @@ constexpr int kMaxRow = 1 << 20;
 constexpr int kMaxCol = 1 << 20;
 constexpr int kDefaultStripWidth = 4;     // columns per block before tuning
 constexpr int kDefaultChunk = 4;          // column nodes per thread before tuning
+constexpr size_t kGraphDefaultMaxNodes = 512 * 512;  // graph-replayed runs by default
+constexpr int64_t kGraphDefaultSteps = 100;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -507,6 +509,9 @@ lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, 
     c->N = N;
     c->stream = (hipStream_t)hip_stream;
     c->red_blocks = rho_delta_blocks(kp);
+    // small meshes, whose kernels take a few microseconds, replay runs of
+    // steps from graphs by default
+    c->graph_steps = N <= kGraphDefaultMaxNodes ? kGraphDefaultSteps : 0;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, LBM_E_DEVICE, "no HIP device");

@@ -542,6 +542,7 @@ def test_graph_replay_matches_launches(case):
                               center=(1023.5, 20.0))
     print("\n[case] graph replay %s" % case, flush=True)
     a = lbm.Solver(p, *init)
+    a.set_graph_steps(0)            # kernel by kernel (small meshes default to graphs)
     b = lbm.Solver(p, *init)
     b.set_graph_steps(9)            # rounded up to 10
     for n in (35, 20, 7):
