@@ -213,17 +213,19 @@ lbm_status lbm_set_velocity(lbm_ctx *c, const double *vx, const double *vy, int 
  * workgroup) in {1, 2, 4, 8, 16} that one workgroup's LDS holds and, for the
  * factorised solve, each chunk length (column nodes per thread) in
  * {4, 8, 16}; for column tiles with windows (see lbm_set_column_shape) of
- * width 4, 8 or 16 and chunk 8 or 16 where the columns are long enough; then
+ * width 4, 8 or 16 and chunk 8 or 16 where the columns are long enough; for
+ * streamed strips of width 8, 16 and 32 where the mesh allows them; then
  * for each collision pass variant of
  * lbm_set_collision_variant that the mesh allows, time `repeats` whole steps
  * (the three passes from the current state into the spare buffers, HIP
  * events), so that every candidate meets the caches as a real step leaves
  * them; keep the fastest of each for the context.  ms[] reports the time
  * per step.  The state f is
- * not changed.  widths[], chunks[] and ms[] (room for 24 entries each, may be
+ * not changed.  widths[], chunks[] and ms[] (room for 27 entries each, may be
  * NULL) receive the candidates and their average time in milliseconds --
  * column candidates as (width, chunk; chunk 0 = general reduction kernel,
- * chunk < 0 = tiles of chunk -chunk), collision candidates as (0, variant)
+ * chunk < 0 = tiles of chunk -chunk, chunk LBM_COLUMN_STREAM = streamed
+ * strips), collision candidates as (0, variant)
  * -- and *count (may be NULL) their number.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int repeats, int *widths, int *chunks, double *ms,
                         int *count);
@@ -254,8 +256,17 @@ lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
  * above and below it (M the carries of the factorised solve: 11, 6, 3) --
  * mirrored about a wall -- so that strips stay wide on long columns (the
  * default for columns of more than 4096 nodes: width 4, chunk 8; tiles of
- * 1712 rows); it needs columns of more than one tile.  LBM_E_INVALID if the
- * shape does not fit.  Results of every shape agree to round-off. */
+ * 1712 rows); it needs columns of more than one tile.  chunk =
+ * LBM_COLUMN_STREAM (width 8, 16 or 32) streams each strip down the columns:
+ * one workgroup per strip walks down it in tiles of 4-node chunks (512
+ * threads), its three chained derivatives pipelined one tile apart, so that
+ * each row of a plane is read and written in whole strip-wide pieces (16
+ * columns: one 128-byte line) and, apart from windows of 144 rows above and
+ * below the column, once; it needs nx a multiple of the width, ny a multiple
+ * of 4 and at least 144, and the chemical-potential force (not the
+ * pseudopotential model).  LBM_E_INVALID if the shape does not fit.  Results
+ * of every shape agree to round-off. */
+#define LBM_COLUMN_STREAM 1
 lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
 
 /* Allocation-free stepping, for callers that cannot allocate device memory

@@ -39,6 +39,7 @@ struct lbm_ctx {
     int64_t graph_steps = 0;
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    size_t lds_max = 0;  // LDS one workgroup may use on the device (bytes)
 };
 
 namespace {
@@ -512,10 +513,14 @@ lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, 
     // small meshes, whose kernels take a few microseconds, replay runs of
     // steps from graphs by default
     c->graph_steps = N <= kGraphDefaultMaxNodes ? kGraphDefaultSteps : 0;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    int lds_max = 0;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+            hipSuccess) {
         delete c;
         return fail(nullptr, LBM_E_DEVICE, "no HIP device");
     }
+    c->lds_max = (size_t)lds_max;
     const size_t bytes = layout_for(p, c->red_blocks).total;
     if (device_ws) {
         if (((uintptr_t)device_ws & 255) != 0) {
@@ -802,7 +807,8 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     const int cand_w[] = {1, 2, 4, 8, 16};
     const int cand_c[] = {4, 8, 16};
     // best_c < 0: tiles with windows of chunk -best_c
-    int n = 0, best_w = c->kp.cols_per_block, best_c = c->kp.col_win ? -c->kp.col_lc : c->kp.col_lc;
+    int n = 0, best_w = c->kp.cols_per_block;
+    int best_c = c->kp.col_stream ? LBM_COLUMN_STREAM : (c->kp.col_win ? -c->kp.col_lc : c->kp.col_lc);
     double best = INFINITY;
     hipError_t err = hipSuccess;
     for (int cw = 0; cw < 15 && err == hipSuccess; ++cw) {
@@ -843,8 +849,28 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
             best_c = -ch;
         }
     }
+    // strips streamed down the columns (reported with chunk LBM_COLUMN_STREAM)
+    const int stream_w[] = {8, 16, 32};
+    for (int i = 0; i < 3 && err == hipSuccess; ++i) {
+        KParams kp = c->kp;
+        if (col_stream_lds(stream_w[i]) > c->lds_max || !set_col_stream(&kp, stream_w[i]))
+            continue;
+        double avg = 0.0;
+        if ((err = steps_ms(kp, &avg)) != hipSuccess) break;
+        if (widths) widths[n] = stream_w[i];
+        if (chunks) chunks[n] = LBM_COLUMN_STREAM;
+        if (ms) ms[n] = avg;
+        ++n;
+        if (avg < best) {
+            best = avg;
+            best_w = stream_w[i];
+            best_c = LBM_COLUMN_STREAM;
+        }
+    }
     if (err == hipSuccess) {
-        if (best_c < 0)
+        if (best_c == LBM_COLUMN_STREAM)
+            (void)set_col_stream(&c->kp, best_w);
+        else if (best_c < 0)
             (void)set_col_tiles(&c->kp, best_w, -best_c);
         else
             set_col_shape(&c->kp, best_w, best_c);
@@ -893,6 +919,16 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
 {
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
+    if (chunk == LBM_COLUMN_STREAM) {
+        KParams kp = c->kp;
+        if (!set_col_stream(&kp, width))
+            return fail(c, LBM_E_INVALID, "streamed strips of this width do not fit this mesh");
+        if (col_stream_lds(width) > c->lds_max)
+            return fail(c, LBM_E_INVALID, "streamed strips need more LDS than a workgroup has");
+        c->kp = kp;
+        drop_graphs(c);
+        return LBM_OK;
+    }
     if (chunk < 0) {
         KParams kp = c->kp;
         if (!set_col_tiles(&kp, width, -chunk))
@@ -902,7 +938,8 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
         return LBM_OK;
     }
     if (chunk != 0 && chunk != 4 && chunk != 8 && chunk != 16)
-        return fail(c, LBM_E_INVALID, "chunk must be 0, 4, 8, 16 or negated for tiles");
+        return fail(c, LBM_E_INVALID,
+                    "chunk must be 0, 4, 8, 16, negated for tiles, or LBM_COLUMN_STREAM");
     KParams kp = c->kp;
     set_col_shape(&kp, width, chunk == 0 ? 4 : chunk);
     if (kp.cols_per_block != width) return fail(c, LBM_E_INVALID, "width does not fit a workgroup");

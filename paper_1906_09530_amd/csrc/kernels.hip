@@ -488,6 +488,7 @@ void set_col_shape(KParams *p, int width, int chunk)
 {
     p->col_win = 0;
     p->col_tile = 0;
+    p->col_stream = 0;
     p->col_lc = chunk;
     iir_carry(*p, chunk, &p->iir_m_col, &p->iir_qL_col);
     // the factorised solve holds up to kMaxColElems nodes of a strip (one
@@ -529,12 +530,33 @@ bool set_col_tiles(KParams *p, int width, int chunk)
     p->iir_m_col = M;
     p->iir_qL_col = qL;
     p->use_iir_cols = 1;
+    p->col_stream = 0;
     p->col_win = 1;
     p->col_tile = hc * chunk;
     p->cols_per_block = width;
     p->col_threads = (width * (hc + 2 * E) + 63) / 64 * 64;
     const int nb = ((p->nx + width - 1) / width) * ((p->ny + p->col_tile - 1) / p->col_tile);
     p->col_xcd_groups = (nb % 8 == 0 && nb >= 64) ? 8 : 1;
+    return true;
+}
+
+bool set_col_stream(KParams *p, int width)
+{
+    if (!col_stream_ok(*p, width)) return false;
+    int M = 0;
+    double qL = 0.0;
+    iir_carry(*p, 4, &M, &qL);
+    if (M > 11) return false;
+    p->col_lc = 4;
+    p->iir_m_col = M;
+    p->iir_qL_col = qL;
+    p->use_iir_cols = 1;
+    p->col_win = 0;
+    p->col_tile = 0;
+    p->col_stream = 1;
+    p->cols_per_block = width;
+    p->col_threads = kMaxBlockThreads;
+    p->col_xcd_groups = 1;
     return true;
 }
 

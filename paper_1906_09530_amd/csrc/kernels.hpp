@@ -43,8 +43,9 @@ struct KParams {
     // chunk length, its power q^LC and the number of carried chunks M
     int use_iir_rows, use_iir_cols, col_lc;
     // column pass over tiles of col_tile rows with windows (col_win; tall
-    // columns), else over whole columns
-    int col_win, col_tile;
+    // columns), streamed down strips in tiles (col_stream), else over whole
+    // columns
+    int col_win, col_tile, col_stream;
     int row_keep;   // collision pass holds f in registers (tuned)
     int row_split;  // collision pass over row segments (tuned; see below)
     int row_win;    // rows beyond one workgroup: every row pass over segments
@@ -118,6 +119,16 @@ bool set_col_tiles(KParams *p, int width, int chunk);
 // window's chunks on each side.
 int col_tile_chunks(int width, int lc);
 int col_window_chunks(int lc);
+// The column pass streamed down strips of `width` columns (8, 16 or 32; 16
+// reads whole 128-byte lines of each row), one workgroup per strip walking
+// down it in tiles of 4-node chunks with the three chained solves pipelined
+// one tile apart.  False (p unchanged) where the mesh does not allow it: the
+// pseudopotential model, nx not a multiple of the width, ny not a multiple
+// of 4 or shorter than the 144-row window.
+bool set_col_stream(KParams *p, int width);
+bool col_stream_ok(const KParams &p, int width);
+// LDS of one streaming workgroup (bytes).
+size_t col_stream_lds(int width);
 
 // ---- batches of independent meshes ------------------------------------
 // Device-side buffers of one mesh of a batch.

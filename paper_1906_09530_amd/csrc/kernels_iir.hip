@@ -594,6 +594,200 @@ __global__ __launch_bounds__(1024) void k_cols_mu_win(KParams p, const double *_
                          fy_out);
 }
 
+// ---- pass B streamed down strips of whole cache lines ------------------
+// A workgroup takes a strip of SW columns (SW = 16: one 128-byte line of each
+// row of a plane) and walks down it in tiles of ST chunks of 4 rows, each of
+// its SW * ST threads holding one chunk of one column.  The three chained
+// solves of the pass (d/dy rho; d2/dy2 rho and so mu; d/dy mu and so F_y) run
+// as a pipeline one tile apart: step s loads the densities of tile s + 1 and
+// finishes the first solve on tile s - 1, the second on tile s - 2 and the
+// third on tile s - 3.  A solve on a tile sums the causal carries of the MC
+// chunks before it, which a ring in LDS keeps from the step before, and the
+// anti-causal carries of the MC chunks after it, which the threads compute
+// from the next tile's values (the previous solve's output of the same
+// step).  The column is one window from kColWin chunks above its first row to
+// kColWin chunks below its last, mirrored about walls (mu - mu_wall odd for
+// wetting walls) or wrapped, as for the tiles above, so each solve is the
+// window solve of iir_solve_window on that window and the stored values are
+// the whole-column ones to round-off.  Every value of a plane is read once
+// (besides the two windows), in whole lines, where strips of whole columns
+// read a quarter of a line per row.
+constexpr int kStreamLC = 4;
+
+template <int SW, int ST>
+struct StreamLds {
+    static constexpr int MC = kCarry(kStreamLC);
+    static constexpr int R = 2 * ST;        // causal carries kept per solve (chunks)
+    static constexpr int NE = ST + MC + 2;  // edge slots: see stream_solve
+    static_assert(ST > MC, "the next tile must hold the chunks whose carries a tile sums");
+    static_assert((R & (R - 1)) == 0, "the carry ring is indexed with a mask");
+    static constexpr int doubles = NE * 4 * SW + 3 * R * SW + (ST + MC) * SW + 3 * 4 * SW;
+};
+
+// Solve k (0, 1, 2) of step s: the derivative d of the thread's chunk of the
+// solve's current tile (s - 1 - k) from its values u, with un the thread's
+// chunk of the next tile.  Edge slots: 0 the previous tile's last chunk (kept
+// in `left` from the step before), 1 + c the current tile's chunk c, ST + 1 + c
+// the next tile's chunk c (c <= MC).  The whole block calls it together.
+template <int SW, int ST>
+__device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int c, int l,
+                                             const double (&u)[kStreamLC],
+                                             const double (&un)[kStreamLC], double *edge,
+                                             double *cPr, double *cB, double *left,
+                                             double (&d)[kStreamLC])
+{
+    constexpr int LC = kStreamLC, MC = StreamLds<SW, ST>::MC, R = StreamLds<SW, ST>::R;
+    auto ES = [&](int slot, int e) { return (slot * 4 + e) * SW + l; };
+#pragma unroll
+    for (int e = 0; e < 4; ++e) edge[ES(1 + c, e)] = u[e];
+    if (c <= MC) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) edge[ES(ST + 1 + c, e)] = un[e];
+    }
+    double *lk = left + k * 4 * SW;  // two buffers of the last two values
+    if (c == 0) {
+        edge[ES(0, 2)] = lk[((s & 1) * 2) * SW + l];
+        edge[ES(0, 3)] = lk[((s & 1) * 2 + 1) * SW + l];
+    }
+    if (c == ST - 1) {
+        lk[(((s + 1) & 1) * 2) * SW + l] = u[LC - 2];
+        lk[(((s + 1) & 1) * 2 + 1) * SW + l] = u[LC - 1];
+    }
+    __syncthreads();
+    // the chunk's own recurrences enter the derivative only as y + z
+    double w[LC], Pc, Bc;
+    {
+        double y[LC], z[LC];
+        iir_chunk<LC>(p, u, edge[ES(c, 2)], edge[ES(c, 3)], edge[ES(c + 2, 0)],
+                      edge[ES(c + 2, 1)], y, z, Pc, Bc);
+#pragma unroll
+        for (int k = 0; k < LC; ++k) w[k] = y[k] + z[k];
+    }
+    // the chunk's index in the window, offset to stay positive in the first
+    // steps (whose tiles lie before the window)
+    const int v = (s - 1 - k) * ST + c + 4 * R;
+    double *cPk = cPr + k * R * SW;
+    cPk[(v & (R - 1)) * SW + l] = Pc;
+    cB[c * SW + l] = Bc;
+    if (c < MC) {
+        // the anti-causal carry of the next tile's chunk c
+        double y2[LC], z2[LC], P2, B2;
+        iir_chunk<LC>(p, un, edge[ES(ST + c, 2)], edge[ES(ST + c, 3)], edge[ES(ST + 2 + c, 0)],
+                      edge[ES(ST + 2 + c, 1)], y2, z2, P2, B2);
+        cB[(ST + c) * SW + l] = B2;
+    }
+    __syncthreads();
+    const double qL = p.iir_qL_col;
+    double Yc = 0.0, Zc = 0.0;
+#pragma unroll
+    for (int mm = MC; mm >= 1; --mm) {
+        Yc = Yc * qL + cPk[((v - mm) & (R - 1)) * SW + l];
+        Zc = Zc * qL + cB[(c + mm) * SW + l];
+    }
+#pragma unroll
+    for (int k = 0; k < LC; ++k)
+        d[k] = p.iir_K * (w[k] + (p.iir_qp[k + 1] * Yc + p.iir_qp[LC - 1 - k] * Zc));
+}
+
+template <int SW, int ST>
+__global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
+                                                            const double *__restrict__ rho,
+                                                            const double *__restrict__ mux,
+                                                            double *__restrict__ mu_out,
+                                                            double *__restrict__ fy_out)
+{
+    constexpr int LC = kStreamLC, E = kColWin<LC>;
+    using S = StreamLds<SW, ST>;
+    extern __shared__ double smem[];
+    double *edge = smem, *cPr = edge + S::NE * 4 * SW, *cB = cPr + 3 * S::R * SW,
+           *left = cB + (ST + S::MC) * SW;
+    // the carries and edges of chunks before the window start from zero
+    for (int i = threadIdx.x; i < S::doubles; i += SW * ST) smem[i] = 0.0;
+    const int nx = p.nx, ny = p.ny;
+    const int c = threadIdx.x / SW, l = threadIdx.x - c * SW;
+    const int col = blockIdx.x * SW + l;  // nx is a multiple of SW
+    const int nc = ny / LC, NV = nc + 2 * E, ntile = (NV + ST - 1) / ST;
+    // the LC values of window chunk v (zero outside the window): its rows
+    // run down from the first one, or up beyond a wall (the mirror image)
+    auto load = [&](const double *__restrict__ src, int v, double (&o)[LC]) {
+        if (v >= 0 && v < NV) {
+            const int y = (v - E) * LC;
+            int r0 = y, dr = 1;
+            if (y < 0) {
+                r0 = p.bc_y ? -1 - y : y + ny;
+                dr = p.bc_y ? -1 : 1;
+            } else if (y >= ny) {
+                r0 = p.bc_y ? 2 * ny - 1 - y : y - ny;
+                dr = p.bc_y ? -1 : 1;
+            }
+            const double *q = src + (ptrdiff_t)r0 * nx + col;
+            const ptrdiff_t st = (ptrdiff_t)dr * nx;
+#pragma unroll
+            for (int k = 0; k < LC; ++k) o[k] = q[k * st];
+        } else {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) o[k] = 0.0;
+        }
+    };
+    // rn: rho of tile s; r1, r2, r3: of tiles s - 1, s - 2, s - 3; a1, a2:
+    // d/dy rho of tiles s - 2, s - 3; m3: the third solve's input on tile s - 3
+    double rn[LC], r1[LC], r2[LC], r3[LC], a1[LC], a2[LC], m3[LC];
+#pragma unroll
+    for (int k = 0; k < LC; ++k) r1[k] = r2[k] = r3[k] = a1[k] = a2[k] = m3[k] = 0.0;
+    load(rho, c, rn);
+    __syncthreads();
+    for (int s = 0; s < ntile + 3; ++s) {
+        double rp[LC], mx[LC];
+        load(rho, (s + 1) * ST + c, rp);
+        load(mux, (s - 2) * ST + c, mx);
+        double d1[LC];
+        stream_solve<SW, ST>(p, 0, s, c, l, r1, rn, edge, cPr, cB, left, d1);
+        // mu on tile s - 2, and the third solve's input there
+        double mw[LC];
+        {
+            double d2[LC];
+            if (!p.kappa_zero) {
+                stream_solve<SW, ST>(p, 1, s, c, l, a1, d1, edge, cPr, cB, left, d2);
+            } else {
+#pragma unroll
+                for (int k = 0; k < LC; ++k) d2[k] = 0.0;
+            }
+            const int v2 = (s - 2) * ST + c, y2 = (v2 - E) * LC;
+            const double sg = (p.bc_y && (y2 < 0 || y2 >= ny)) ? -1.0 : 1.0;
+            double m[LC];
+#pragma unroll
+            for (int k = 0; k < LC; ++k) {
+                m[k] = mx[k];
+                if (!p.kappa_zero) m[k] -= p.kappa * d2[k];
+                mw[k] = p.wet ? sg * (m[k] - p.mu_wall) : m[k];
+            }
+            if (v2 >= E && v2 < E + nc) {
+                double *q = mu_out + (ptrdiff_t)y2 * nx + col;
+#pragma unroll
+                for (int k = 0; k < LC; ++k) q[(ptrdiff_t)k * nx] = m[k];
+            }
+        }
+        double d3[LC];
+        stream_solve<SW, ST>(p, 2, s, c, l, m3, mw, edge, cPr, cB, left, d3);
+        const int v3 = (s - 3) * ST + c;
+        if (v3 >= E && v3 < E + nc) {
+            double *q = fy_out + (ptrdiff_t)(v3 - E) * LC * nx + col;
+#pragma unroll
+            for (int k = 0; k < LC; ++k) q[(ptrdiff_t)k * nx] = -r3[k] * d3[k] + CS2 * a2[k];
+        }
+#pragma unroll
+        for (int k = 0; k < LC; ++k) {
+            r3[k] = r2[k];
+            r2[k] = r1[k];
+            r1[k] = rn[k];
+            rn[k] = rp[k];
+            a2[k] = a1[k];
+            a1[k] = d1[k];
+            m3[k] = mw[k];
+        }
+    }
+}
+
 // Pass C on rows [y0, y0 + rows_per_block) of one mesh.
 // KEEP: the nine populations stay in registers from the first read to the
 // collision; otherwise each is read again when needed (fewer registers, so
@@ -1212,9 +1406,41 @@ int col_window_chunks(int lc)
     return lc == 4 ? kColWin<4> : (lc == 8 ? kColWin<8> : kColWin<16>);
 }
 
+template <int SW, int ST>
+static hipError_t launch_stream(const KParams &p, const double *rho, const double *mux,
+                                double *mu, double *fy, hipStream_t s)
+{
+    const size_t lds = col_stream_lds(SW);
+    hipLaunchKernelGGL((k_cols_mu_stream<SW, ST>), dim3(p.nx / SW), dim3(SW * ST), lds, s, p, rho,
+                       mux, mu, fy);
+    return hipGetLastError();
+}
+
+size_t col_stream_lds(int width)
+{
+    const int d = width == 8 ? StreamLds<8, 64>::doubles
+                             : (width == 32 ? StreamLds<32, 16>::doubles : StreamLds<16, 32>::doubles);
+    return sizeof(double) * (size_t)d;
+}
+
+bool col_stream_ok(const KParams &p, int width)
+{
+    return !p.sc && (width == 8 || width == 16 || width == 32) && p.nx % width == 0 &&
+           p.ny % kStreamLC == 0 && p.ny >= kColWin<kStreamLC> * kStreamLC &&
+           p.ny >= kFastMinLine;
+}
+
 hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
                               double *fy, hipStream_t s)
 {
+    if (p.col_stream) {
+        if (!col_stream_ok(p, p.cols_per_block)) return hipErrorInvalidValue;
+        switch (p.cols_per_block) {
+        case 8: return launch_stream<8, 64>(p, rho, mux, mu, fy, s);
+        case 32: return launch_stream<32, 16>(p, rho, mux, mu, fy, s);
+        default: return launch_stream<16, 32>(p, rho, mux, mu, fy, s);
+        }
+    }
     if (p.col_win) {
         const int W = p.cols_per_block, nw = p.col_tile / p.col_lc + 2 * col_window_chunks(p.col_lc);
         const int nb = ((p.nx + W - 1) / W) * ((p.ny + p.col_tile - 1) / p.col_tile);

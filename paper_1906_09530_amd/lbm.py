@@ -36,6 +36,7 @@ class Params(C.Structure):
 
 
 COLLISION_BGK, COLLISION_MRT = 0, 1
+COLUMN_STREAM = 1  # lbm_set_column_shape chunk: strips streamed down the columns
 FORCE_CP, FORCE_SC = 0, 1
 # MRT relaxation rates s_e, s_eps, s_q of the paper (Sec. 2, after Eq. 4)
 MRT_RATES = (1.64, 1.54, 1.9)
@@ -286,10 +287,11 @@ class Solver:
     def autotune(self, repeats=20):
         """Pick the fastest column-pass shape and collision variant; returns
         {(width, chunk): ms} (chunk 0: the general reduction kernel; chunk < 0:
-        tiles with windows; (0, v): collision variant v)."""
-        w = (C.c_int * 24)()
-        ch = (C.c_int * 24)()
-        ms = (C.c_double * 24)()
+        tiles with windows; chunk COLUMN_STREAM: streamed strips; (0, v):
+        collision variant v)."""
+        w = (C.c_int * 27)()
+        ch = (C.c_int * 27)()
+        ms = (C.c_double * 27)()
         n = C.c_int()
         _check(load().lbm_autotune(self.ctx, int(repeats), w, ch, ms, C.byref(n)), self.ctx)
         return {(w[i], ch[i]): ms[i] for i in range(n.value)}
@@ -302,7 +304,8 @@ class Solver:
 
     def set_column_shape(self, width, chunk):
         """Strip width and chunk of the column pass (chunk 0: general
-        reduction kernel; negative: tiles with windows)."""
+        reduction kernel; negative: tiles with windows; COLUMN_STREAM: strips
+        of 8, 16 or 32 columns streamed down the columns in tiles)."""
         _check(load().lbm_set_column_shape(self.ctx, int(width), int(chunk)), self.ctx)
 
     def get_state(self, device=False):

@@ -125,6 +125,7 @@ def test_every_column_shape_matches_oracle(walls, nx, ny):
     fm = max(np.abs(fx2).max(), np.abs(fy2).max())
     s = lbm.Solver(p, rho0, ux0, uy0)
     shapes = [(w, c) for w in (1, 2, 4, 8, 16) for c in (0, 4, 8, 16)]
+    shapes += [(w, lbm.COLUMN_STREAM) for w in (8, 16, 32)]
     tried = 0
     for w, c in shapes:
         try:
@@ -138,9 +139,10 @@ def test_every_column_shape_matches_oracle(walls, nx, ny):
         assert np.abs(mu - mu2).max() <= 1e-12 * np.abs(mu2).max()
         assert np.abs(fy - fy2).max() <= 1e-12 * fm
         assert np.abs(fx - fx2).max() <= 1e-12 * fm
-    assert tried >= (10 if ny <= 256 else 6)
+    assert tried >= (13 if ny <= 256 else 9)
     table = s.autotune(3)
-    assert len(table) >= (10 if ny <= 256 else 6)
+    assert len(table) >= (13 if ny <= 256 else 9)
+    assert sum(1 for (w, c) in table if c == lbm.COLUMN_STREAM and w > 0) == 3
     mu, fx, fy = s.force_fields()
     assert np.abs(fy - fy2).max() <= 1e-12 * fm
 
@@ -506,6 +508,91 @@ def test_full_size_1000_steps(name, golden_dir):
     d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
     s = lbm.Solver(p, *d)
     s.autotune(3)
+    s.step(int(gold["steps"]))
+    r, vx, vy = s.moments()
+    s.close()
+    idx = gold["idx"]
+    er = float(np.max(np.abs(r.ravel()[idx] - gold["rho"]) / np.abs(gold["rho"])))
+    ev = float(max(np.abs(vx.ravel()[idx] - gold["vx"]).max(),
+                   np.abs(vy.ravel()[idx] - gold["vy"]).max()) / float(gold["vmax"]))
+    print("  %d nodes: rel err rho %.2e, v %.2e" % (len(idx), er, ev), flush=True)
+    assert er <= TOL and ev <= TOL
+
+
+@pytest.mark.parametrize("case", ["periodic16", "walls_wetting16", "kappa0_walls8",
+                                  "walls32_shortest"])
+def test_column_stream_matches_oracle(case):
+    """The column pass streamed down strips (lbm_set_column_shape with chunk
+    LBM_COLUMN_STREAM): periodic 1000-node columns, 16 wide (a window of 322
+    chunks, the last tile ragged); 2048-node columns between wetting walls,
+    16 wide (mu - mu_wall odd beyond the walls); kappa = 0 between walls,
+    8 wide (one derivative before mu);
+    148-node columns between walls, 32 wide (the shortest columns whose
+    144-row windows reflect once).  Parity with the oracle after 40 steps,
+    and the whole-column shape agrees to round-off."""
+    kw = dict()
+    if case == "periodic16":
+        nx, ny, width = 32, 1000, 16
+    elif case == "walls_wetting16":
+        nx, ny, width, kw = 48, 2048, 16, dict(bc_y=1, wetting=1, mu_wall=-0.05)
+    elif case == "kappa0_walls8":
+        nx, ny, width, kw = 16, 600, 8, dict(bc_y=1)
+    else:
+        nx, ny, width, kw = 64, 148, 32, dict(bc_y=1)
+    kappa = 0.0 if case == "kappa0_walls8" else 0.1
+    p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=kappa, tau=0.8, k=0.2, mu_cap=6.0,
+                         **kw)
+    g, l = A.coexistence(p.eos, p.T_r)
+    rho0, ux0, uy0 = inputs.slab(nx, ny, g, l, 3.0, seed=9, noise=1e-4)
+    # interfaces a few nodes from tile edges and, between walls, the liquid
+    # against the bottom wall
+    rho0 = np.ascontiguousarray(np.roll(rho0, ny // 4 - 3, axis=0))
+    print("\n[case] column stream %s %dx%d width %d" % (case, nx, ny, width), flush=True)
+    ref = _oracle_after(op, rho0, ux0, uy0, [40])
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    s.set_column_shape(width, lbm.COLUMN_STREAM)
+    s.step(40)
+    er, ev = _errors(s.moments(), ref[40])
+    print("  rel err rho %.2e, v %.2e" % (er, ev), flush=True)
+    assert er <= TOL and ev <= TOL
+    b = lbm.Solver(p, rho0, ux0, uy0)
+    b.set_column_shape(1, 4 if ny % 8 else 8)     # whole columns
+    b.step(40)
+    er2, ev2 = _errors(s.moments(), b.moments())
+    assert er2 <= 1e-12 and ev2 <= 1e-10
+    s.close()
+    b.close()
+
+
+def test_column_stream_rejects_what_it_cannot_take():
+    """Streamed strips need nx a multiple of the width, ny a multiple of 4 of
+    at least 144 nodes, and the chemical-potential force."""
+    cases = [(lbm.EOS_CS, 40, 256, 16, {}),          # nx not a multiple of 16
+             (lbm.EOS_CS, 64, 140, 16, {}),          # columns shorter than the window
+             (lbm.EOS_CS, 64, 150, 16, {}),          # ny not a multiple of 4
+             (lbm.EOS_CS, 64, 256, 4, {}),           # width
+             (lbm.EOS_CS, 64, 256, 16, dict(force=lbm.FORCE_SC))]
+    for eos, nx, ny, width, kw in cases:
+        p = lbm.params(eos, 0.7, nx, ny, kappa=0.1, tau=0.8, k=0.2, mu_cap=6.0, **kw)
+        g, l = A.coexistence(eos, 0.7)
+        s = lbm.Solver(p, *inputs.slab(nx, ny, g, l, 3.0, seed=1, noise=0.0))
+        with pytest.raises(lbm.LBMError):
+            s.set_column_shape(width, lbm.COLUMN_STREAM)
+        s.close()
+
+
+def test_column_stream_full_size_splash(golden_dir):
+    """The 4096 x 2048 CS splash between walls with the column pass streamed
+    down 16-column strips: 1000 steps against the oracle's fields at the
+    sampled nodes of the full-size golden file (as the autotuned test)."""
+    import torch
+    name = "cs4096x2048walls"
+    gold = np.load(os.path.join(golden_dir, "fullsize_%s.npz" % name))
+    p, (rho0, ux0, uy0) = _fullsize_case(name)
+    print("\n[case] %s streamed columns, 1000 steps" % name, flush=True)
+    d = [torch.from_numpy(a).cuda() for a in (rho0, ux0, uy0)]
+    s = lbm.Solver(p, *d)
+    s.set_column_shape(16, lbm.COLUMN_STREAM)
     s.step(int(gold["steps"]))
     r, vx, vy = s.moments()
     s.close()
