@@ -853,7 +853,7 @@ lbm_status lbm_autotune(lbm_ctx *c, int repeats, int *widths, int *chunks, doubl
     const int stream_w[] = {8, 16, 32};
     for (int i = 0; i < 3 && err == hipSuccess; ++i) {
         KParams kp = c->kp;
-        if (col_stream_lds(stream_w[i]) > c->lds_max || !set_col_stream(&kp, stream_w[i]))
+        if (!set_col_stream(&kp, stream_w[i]) || col_stream_lds(stream_w[i], kp.col_lc) > c->lds_max)
             continue;
         double avg = 0.0;
         if ((err = steps_ms(kp, &avg)) != hipSuccess) break;
@@ -923,7 +923,7 @@ lbm_status lbm_set_column_shape(lbm_ctx *c, int width, int chunk)
         KParams kp = c->kp;
         if (!set_col_stream(&kp, width))
             return fail(c, LBM_E_INVALID, "streamed strips of this width do not fit this mesh");
-        if (col_stream_lds(width) > c->lds_max)
+        if (col_stream_lds(width, kp.col_lc) > c->lds_max)
             return fail(c, LBM_E_INVALID, "streamed strips need more LDS than a workgroup has");
         c->kp = kp;
         drop_graphs(c);

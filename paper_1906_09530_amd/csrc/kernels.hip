@@ -543,11 +543,12 @@ bool set_col_tiles(KParams *p, int width, int chunk)
 bool set_col_stream(KParams *p, int width)
 {
     if (!col_stream_ok(*p, width)) return false;
+    const int lc = col_stream_chunk(p->ny);
     int M = 0;
     double qL = 0.0;
-    iir_carry(*p, 4, &M, &qL);
-    if (M > 11) return false;
-    p->col_lc = 4;
+    iir_carry(*p, lc, &M, &qL);
+    if (M > (lc == 8 ? 6 : 11)) return false;
+    p->col_lc = lc;
     p->iir_m_col = M;
     p->iir_qL_col = qL;
     p->use_iir_cols = 1;
@@ -555,7 +556,7 @@ bool set_col_stream(KParams *p, int width)
     p->col_tile = 0;
     p->col_stream = 1;
     p->cols_per_block = width;
-    p->col_threads = kMaxBlockThreads;
+    p->col_threads = 512;
     p->col_xcd_groups = 1;
     return true;
 }

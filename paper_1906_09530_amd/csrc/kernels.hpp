@@ -121,14 +121,16 @@ int col_tile_chunks(int width, int lc);
 int col_window_chunks(int lc);
 // The column pass streamed down strips of `width` columns (8, 16 or 32; 16
 // reads whole 128-byte lines of each row), one workgroup per strip walking
-// down it in tiles of 4-node chunks with the three chained solves pipelined
-// one tile apart.  False (p unchanged) where the mesh does not allow it: the
-// pseudopotential model, nx not a multiple of the width, ny not a multiple
-// of 4 or shorter than the 144-row window.
+// down it in tiles of chunks (8 nodes where ny is a multiple of 8, else 4)
+// with the three chained solves pipelined one tile apart.  False (p
+// unchanged) where the mesh does not allow it: the pseudopotential model, nx
+// not a multiple of the width, ny not a multiple of 4 or shorter than the
+// window (168 rows with 8-node chunks, 144 with 4).
 bool set_col_stream(KParams *p, int width);
 bool col_stream_ok(const KParams &p, int width);
-// LDS of one streaming workgroup (bytes).
-size_t col_stream_lds(int width);
+int col_stream_chunk(int ny);
+// LDS of one streaming workgroup (bytes) for chunk length lc.
+size_t col_stream_lds(int width, int lc);
 
 // ---- batches of independent meshes ------------------------------------
 // Device-side buffers of one mesh of a batch.

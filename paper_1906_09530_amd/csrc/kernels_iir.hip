@@ -596,7 +596,7 @@ __global__ __launch_bounds__(1024) void k_cols_mu_win(KParams p, const double *_
 
 // ---- pass B streamed down strips of whole cache lines ------------------
 // A workgroup takes a strip of SW columns (SW = 16: one 128-byte line of each
-// row of a plane) and walks down it in tiles of ST chunks of 4 rows, each of
+// row of a plane) and walks down it in tiles of ST chunks of LC rows, each of
 // its SW * ST threads holding one chunk of one column.  The three chained
 // solves of the pass (d/dy rho; d2/dy2 rho and so mu; d/dy mu and so F_y) run
 // as a pipeline one tile apart: step s loads the densities of tile s + 1 and
@@ -611,12 +611,11 @@ __global__ __launch_bounds__(1024) void k_cols_mu_win(KParams p, const double *_
 // window solve of iir_solve_window on that window and the stored values are
 // the whole-column ones to round-off.  Every value of a plane is read once
 // (besides the two windows), in whole lines, where strips of whole columns
-// read a quarter of a line per row.
-constexpr int kStreamLC = 4;
-
-template <int SW, int ST>
+// read a quarter of a line per row.  512 threads: the carried tiles take
+// ~240 registers with 8-node chunks, and a 1024-thread workgroup would spill.
+template <int SW, int ST, int LC>
 struct StreamLds {
-    static constexpr int MC = kCarry(kStreamLC);
+    static constexpr int MC = kCarry(LC);
     static constexpr int R = 2 * ST;        // causal carries kept per solve (chunks)
     static constexpr int NE = ST + MC + 2;  // edge slots: see stream_solve
     static_assert(ST > MC, "the next tile must hold the chunks whose carries a tile sums");
@@ -629,20 +628,21 @@ struct StreamLds {
 // chunk of the next tile.  Edge slots: 0 the previous tile's last chunk (kept
 // in `left` from the step before), 1 + c the current tile's chunk c, ST + 1 + c
 // the next tile's chunk c (c <= MC).  The whole block calls it together.
-template <int SW, int ST>
+template <int SW, int ST, int LC>
 __device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int c, int l,
-                                             const double (&u)[kStreamLC],
-                                             const double (&un)[kStreamLC], double *edge,
+                                             const double (&u)[LC],
+                                             const double (&un)[LC], double *edge,
                                              double *cPr, double *cB, double *left,
-                                             double (&d)[kStreamLC])
+                                             double (&d)[LC])
 {
-    constexpr int LC = kStreamLC, MC = StreamLds<SW, ST>::MC, R = StreamLds<SW, ST>::R;
+    constexpr int MC = StreamLds<SW, ST, LC>::MC, R = StreamLds<SW, ST, LC>::R;
     auto ES = [&](int slot, int e) { return (slot * 4 + e) * SW + l; };
+    auto EI = [](int e) { return e < 2 ? e : LC - 4 + e; };
 #pragma unroll
-    for (int e = 0; e < 4; ++e) edge[ES(1 + c, e)] = u[e];
+    for (int e = 0; e < 4; ++e) edge[ES(1 + c, e)] = u[EI(e)];
     if (c <= MC) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) edge[ES(ST + 1 + c, e)] = un[e];
+        for (int e = 0; e < 4; ++e) edge[ES(ST + 1 + c, e)] = un[EI(e)];
     }
     double *lk = left + k * 4 * SW;  // two buffers of the last two values
     if (c == 0) {
@@ -689,15 +689,15 @@ __device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int
         d[k] = p.iir_K * (w[k] + (p.iir_qp[k + 1] * Yc + p.iir_qp[LC - 1 - k] * Zc));
 }
 
-template <int SW, int ST>
+template <int SW, int ST, int LC>
 __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
                                                             const double *__restrict__ rho,
                                                             const double *__restrict__ mux,
                                                             double *__restrict__ mu_out,
                                                             double *__restrict__ fy_out)
 {
-    constexpr int LC = kStreamLC, E = kColWin<LC>;
-    using S = StreamLds<SW, ST>;
+    constexpr int E = kColWin<LC>;
+    using S = StreamLds<SW, ST, LC>;
     extern __shared__ double smem[];
     double *edge = smem, *cPr = edge + S::NE * 4 * SW, *cB = cPr + 3 * S::R * SW,
            *left = cB + (ST + S::MC) * SW;
@@ -737,17 +737,26 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
     load(rho, c, rn);
     __syncthreads();
     for (int s = 0; s < ntile + 3; ++s) {
+        // solve k runs on tile s - 1 - k when that tile is in the window (a
+        // tile before it would only meet zeros; after it, nothing is stored)
+        const bool run0 = s >= 1 && s <= ntile, run1 = s >= 2 && s <= ntile + 1 && !p.kappa_zero,
+                   run2 = s >= 3;
         double rp[LC], mx[LC];
         load(rho, (s + 1) * ST + c, rp);
         load(mux, (s - 2) * ST + c, mx);
         double d1[LC];
-        stream_solve<SW, ST>(p, 0, s, c, l, r1, rn, edge, cPr, cB, left, d1);
+        if (run0) {
+            stream_solve<SW, ST, LC>(p, 0, s, c, l, r1, rn, edge, cPr, cB, left, d1);
+        } else {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) d1[k] = 0.0;
+        }
         // mu on tile s - 2, and the third solve's input there
         double mw[LC];
         {
             double d2[LC];
-            if (!p.kappa_zero) {
-                stream_solve<SW, ST>(p, 1, s, c, l, a1, d1, edge, cPr, cB, left, d2);
+            if (run1) {
+                stream_solve<SW, ST, LC>(p, 1, s, c, l, a1, d1, edge, cPr, cB, left, d2);
             } else {
 #pragma unroll
                 for (int k = 0; k < LC; ++k) d2[k] = 0.0;
@@ -768,7 +777,12 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
             }
         }
         double d3[LC];
-        stream_solve<SW, ST>(p, 2, s, c, l, m3, mw, edge, cPr, cB, left, d3);
+        if (run2) {
+            stream_solve<SW, ST, LC>(p, 2, s, c, l, m3, mw, edge, cPr, cB, left, d3);
+        } else {
+#pragma unroll
+            for (int k = 0; k < LC; ++k) d3[k] = 0.0;
+        }
         const int v3 = (s - 3) * ST + c;
         if (v3 >= E && v3 < E + nc) {
             double *q = fy_out + (ptrdiff_t)(v3 - E) * LC * nx + col;
@@ -1406,28 +1420,38 @@ int col_window_chunks(int lc)
     return lc == 4 ? kColWin<4> : (lc == 8 ? kColWin<8> : kColWin<16>);
 }
 
-template <int SW, int ST>
+template <int SW, int ST, int LC>
 static hipError_t launch_stream(const KParams &p, const double *rho, const double *mux,
                                 double *mu, double *fy, hipStream_t s)
 {
-    const size_t lds = col_stream_lds(SW);
-    hipLaunchKernelGGL((k_cols_mu_stream<SW, ST>), dim3(p.nx / SW), dim3(SW * ST), lds, s, p, rho,
-                       mux, mu, fy);
+    const size_t lds = sizeof(double) * StreamLds<SW, ST, LC>::doubles;
+    hipLaunchKernelGGL((k_cols_mu_stream<SW, ST, LC>), dim3(p.nx / SW), dim3(SW * ST), lds, s, p,
+                       rho, mux, mu, fy);
     return hipGetLastError();
 }
 
-size_t col_stream_lds(int width)
+// Chunk length of the streamed column pass: 8 nodes where the columns are
+// whole 8-node chunks, else 4.
+int col_stream_chunk(int ny) { return ny % 8 == 0 ? 8 : 4; }
+
+size_t col_stream_lds(int width, int lc)
 {
-    const int d = width == 8 ? StreamLds<8, 64>::doubles
-                             : (width == 32 ? StreamLds<32, 16>::doubles : StreamLds<16, 32>::doubles);
+    int d = 0;
+    if (lc == 8)
+        d = width == 8 ? StreamLds<8, 64, 8>::doubles
+                       : (width == 32 ? StreamLds<32, 16, 8>::doubles : StreamLds<16, 32, 8>::doubles);
+    else
+        d = width == 8 ? StreamLds<8, 64, 4>::doubles
+                       : (width == 32 ? StreamLds<32, 16, 4>::doubles : StreamLds<16, 32, 4>::doubles);
     return sizeof(double) * (size_t)d;
 }
 
 bool col_stream_ok(const KParams &p, int width)
 {
+    const int lc = col_stream_chunk(p.ny);
+    const int win = lc == 8 ? kColWin<8> * 8 : kColWin<4> * 4;
     return !p.sc && (width == 8 || width == 16 || width == 32) && p.nx % width == 0 &&
-           p.ny % kStreamLC == 0 && p.ny >= kColWin<kStreamLC> * kStreamLC &&
-           p.ny >= kFastMinLine;
+           p.ny % 4 == 0 && p.ny >= win && p.ny >= kFastMinLine;
 }
 
 hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,
@@ -1435,10 +1459,18 @@ hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double 
 {
     if (p.col_stream) {
         if (!col_stream_ok(p, p.cols_per_block)) return hipErrorInvalidValue;
+        if (p.col_lc != col_stream_chunk(p.ny)) return hipErrorInvalidValue;
+        if (p.col_lc == 8) {
+            switch (p.cols_per_block) {
+            case 8: return launch_stream<8, 64, 8>(p, rho, mux, mu, fy, s);
+            case 32: return launch_stream<32, 16, 8>(p, rho, mux, mu, fy, s);
+            default: return launch_stream<16, 32, 8>(p, rho, mux, mu, fy, s);
+            }
+        }
         switch (p.cols_per_block) {
-        case 8: return launch_stream<8, 64>(p, rho, mux, mu, fy, s);
-        case 32: return launch_stream<32, 16>(p, rho, mux, mu, fy, s);
-        default: return launch_stream<16, 32>(p, rho, mux, mu, fy, s);
+        case 8: return launch_stream<8, 64, 4>(p, rho, mux, mu, fy, s);
+        case 32: return launch_stream<32, 16, 4>(p, rho, mux, mu, fy, s);
+        default: return launch_stream<16, 32, 4>(p, rho, mux, mu, fy, s);
         }
     }
     if (p.col_win) {

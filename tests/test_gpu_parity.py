@@ -519,26 +519,31 @@ def test_full_size_1000_steps(name, golden_dir):
     assert er <= TOL and ev <= TOL
 
 
-@pytest.mark.parametrize("case", ["periodic16", "walls_wetting16", "kappa0_walls8",
-                                  "walls32_shortest"])
+@pytest.mark.parametrize("case", ["periodic16_lc4", "periodic16_lc8", "walls_wetting16",
+                                  "kappa0_walls8", "walls32_shortest4", "walls16_shortest8"])
 def test_column_stream_matches_oracle(case):
     """The column pass streamed down strips (lbm_set_column_shape with chunk
-    LBM_COLUMN_STREAM): periodic 1000-node columns, 16 wide (a window of 322
-    chunks, the last tile ragged); 2048-node columns between wetting walls,
-    16 wide (mu - mu_wall odd beyond the walls); kappa = 0 between walls,
-    8 wide (one derivative before mu);
-    148-node columns between walls, 32 wide (the shortest columns whose
-    144-row windows reflect once).  Parity with the oracle after 40 steps,
-    and the whole-column shape agrees to round-off."""
+    LBM_COLUMN_STREAM; 8-node chunks where ny is a multiple of 8, else 4):
+    periodic columns of 1004 (4-node chunks) and 1000 nodes (8-node), 16
+    wide, the last tile ragged; 2048-node columns between wetting walls, 16
+    wide (mu - mu_wall odd beyond the walls); kappa = 0 between walls, 8 wide
+    (one derivative before mu); the shortest columns whose windows reflect
+    once between walls: 148 nodes 32 wide (4-node chunks, 144-row windows)
+    and 168 nodes 16 wide (8-node, 168).  Parity with the oracle after 40
+    steps, and the whole-column shape agrees to round-off."""
     kw = dict()
-    if case == "periodic16":
+    if case == "periodic16_lc4":
+        nx, ny, width = 32, 1004, 16
+    elif case == "periodic16_lc8":
         nx, ny, width = 32, 1000, 16
     elif case == "walls_wetting16":
         nx, ny, width, kw = 48, 2048, 16, dict(bc_y=1, wetting=1, mu_wall=-0.05)
     elif case == "kappa0_walls8":
         nx, ny, width, kw = 16, 600, 8, dict(bc_y=1)
-    else:
+    elif case == "walls32_shortest4":
         nx, ny, width, kw = 64, 148, 32, dict(bc_y=1)
+    else:
+        nx, ny, width, kw = 32, 168, 16, dict(bc_y=1)
     kappa = 0.0 if case == "kappa0_walls8" else 0.1
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=kappa, tau=0.8, k=0.2, mu_cap=6.0,
                          **kw)
@@ -565,10 +570,12 @@ def test_column_stream_matches_oracle(case):
 
 
 def test_column_stream_rejects_what_it_cannot_take():
-    """Streamed strips need nx a multiple of the width, ny a multiple of 4 of
-    at least 144 nodes, and the chemical-potential force."""
+    """Streamed strips need nx a multiple of the width, ny a multiple of 4 at
+    least as long as the window (144 rows with 4-node chunks, 168 with 8-node
+    chunks where ny is a multiple of 8), and the chemical-potential force."""
     cases = [(lbm.EOS_CS, 40, 256, 16, {}),          # nx not a multiple of 16
-             (lbm.EOS_CS, 64, 140, 16, {}),          # columns shorter than the window
+             (lbm.EOS_CS, 64, 140, 16, {}),          # shorter than the 144-row window
+             (lbm.EOS_CS, 64, 160, 16, {}),          # shorter than the 168-row window
              (lbm.EOS_CS, 64, 150, 16, {}),          # ny not a multiple of 4
              (lbm.EOS_CS, 64, 256, 4, {}),           # width
              (lbm.EOS_CS, 64, 256, 16, dict(force=lbm.FORCE_SC))]
