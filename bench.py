@@ -38,7 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # Bytes per node of each kernel (FP64) as this design moves them:
 #   row pass A: read the three density groups of the state (3 x 8), write rho
 #     and the row part of mu (2 x 8)
-#   column pass B: read rho and the row part of mu; write mu, F_y
+#   column pass B: read rho and the row part of mu; write mu, F_y (strips
+#     streamed down long columns add their windows: 168 rows above and
+#     below, ~2.6 B per node at 2048 rows)
 #   row pass C: read f (9 x 8), mu, F_y; write f (9 x 8) and its three
 #     density groups (3 x 8); over row segments (long rows) it also reads
 #     rho (8), and the window's 52 nodes past each end of an 896-node
@@ -380,6 +382,7 @@ def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
     return {"workload": "drop splashing on a 40-node film between walls, CS, 4096x2048, "
                         "T/Tc=0.6, R=100, tau=0.6, k=0.2, kappa=0.1",
             "nx": nx, "ny": ny, "finite": finite, "steps": steps, "collision_variant": variant,
+            "column_shape": column_shape(tune),
             "ms_per_step": round(ms_step, 6), "MLUPS": round(N / (ms_step * 1e-3) / 1e6, 1),
             "floor_equivalent_GB_s": round(FLOOR_BYTES * N / (ms_step * 1e-3) / 1e9, 1),
             "kernels": {names[i]: {"avg_ms": round(ms[i], 6),
@@ -387,6 +390,13 @@ def splash_hbm(torch, lbm, inputs, steps=300, kernel_steps=200):
                                    "design_GB_s": round(nbytes[i] * N / (ms[i] * 1e-3) / 1e9, 1)}
                         for i in range(len(ms))},
             "dominant": names[dom], "dominant_ms": ms[dom]}
+
+
+def column_shape(tune):
+    """The column-pass shape the autotuner kept, as [width, chunk] (chunk
+    LBM_COLUMN_STREAM = 1: strips streamed down the columns; negative: tiles
+    with windows; 0: the reduction kernel)."""
+    return list(min((k for k in tune if k[0] > 0), key=tune.get))
 
 
 def small_mesh_bench(torch, lbm, inputs, steps=2000):
@@ -439,7 +449,7 @@ def large_mesh_bench(torch, lbm, inputs, steps=200):
     s = lbm.Solver(p, *d, stream=stream.cuda_stream)
     del d
     s.step(10)
-    s.autotune(2)
+    tune = s.autotune(2)
     s.step(10)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -457,6 +467,7 @@ def large_mesh_bench(torch, lbm, inputs, steps=200):
             "nx": nx, "ny": ny, "steps": steps, "finite": finite,
             "device_bytes": ws, "ms_per_step": round(ms, 4),
             "MLUPS": round(nx * ny / (ms * 1e-3) / 1e6, 1),
+            "column_shape": column_shape(tune),
             "kernels_ms": {n: round(t, 4) for n, t in zip(SEG_NAMES, kms)}}
 
 
