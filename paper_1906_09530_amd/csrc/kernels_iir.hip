@@ -605,14 +605,16 @@ __global__ __launch_bounds__(1024) void k_cols_mu_win(KParams p, const double *_
 // chunks before it, which a ring in LDS keeps from the step before, and the
 // anti-causal carries of the MC chunks after it, which the threads compute
 // from the next tile's values (the previous solve's output of the same
-// step).  The column is one window from kColWin chunks above its first row to
-// kColWin chunks below its last, mirrored about walls (mu - mu_wall odd for
-// wetting walls) or wrapped, as for the tiles above, so each solve is the
-// window solve of iir_solve_window on that window and the stored values are
-// the whole-column ones to round-off.  Every value of a plane is read once
-// (besides the two windows), in whole lines, where strips of whole columns
-// read a quarter of a line per row.  512 threads: the carried tiles take
-// ~240 registers with 8-node chunks, and a 1024-thread workgroup would spill.
+// step).  Between walls each solve closes at the walls as the whole-column
+// solve does, with the mirror image's edge values and carries; a periodic
+// column is one window from kColWin chunks above its first row to kColWin
+// chunks below its last, wrapped, as for the tiles above, so each solve is
+// the window solve of iir_solve_window on that window.  Either way the stored
+// values are the whole-column ones to round-off.  Every value of a plane is
+// read once (besides a periodic column's two windows), in whole lines, where
+// strips of whole columns read a quarter of a line per row.  512 threads: the
+// carried tiles take ~240 registers with 8-node chunks, and a 1024-thread
+// workgroup would spill.
 template <int SW, int ST, int LC>
 struct StreamLds {
     static constexpr int MC = kCarry(LC);
@@ -620,20 +622,26 @@ struct StreamLds {
     static constexpr int NE = ST + MC + 2;  // edge slots: see stream_solve
     static_assert(ST > MC, "the next tile must hold the chunks whose carries a tile sums");
     static_assert((R & (R - 1)) == 0, "the carry ring is indexed with a mask");
-    static constexpr int doubles = NE * 4 * SW + 3 * R * SW + (ST + MC) * SW + 3 * 4 * SW;
+    static constexpr int doubles = NE * 4 * SW + 3 * R * SW + (ST + MC) * SW + 3 * 4 * SW + MC * SW;
 };
 
 // Solve k (0, 1, 2) of step s: the derivative d of the thread's chunk of the
 // solve's current tile (s - 1 - k) from its values u, with un the thread's
 // chunk of the next tile.  Edge slots: 0 the previous tile's last chunk (kept
 // in `left` from the step before), 1 + c the current tile's chunk c, ST + 1 + c
-// the next tile's chunk c (c <= MC).  The whole block calls it together.
+// the next tile's chunk c (c <= MC).  Between walls (wall) the chunks are the
+// column's own nc chunks, and the chunks next to a wall take the edge values
+// and the carries of the chunks beyond it from the mirror image of u (parity
+// par), as the whole-column solve's ghost chunks do: the carry of the image
+// of chunk i is -par B_i / q before the first wall and -par q P_i after the
+// last (lookP holds the next tile's P for images that fall there).  The whole
+// block calls it together.
 template <int SW, int ST, int LC>
-__device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int c, int l,
-                                             const double (&u)[LC],
+__device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int c, int l, int nc,
+                                             bool wall, double par, const double (&u)[LC],
                                              const double (&un)[LC], double *edge,
                                              double *cPr, double *cB, double *left,
-                                             double (&d)[LC])
+                                             double *lookP, double (&d)[LC])
 {
     constexpr int MC = StreamLds<SW, ST, LC>::MC, R = StreamLds<SW, ST, LC>::R;
     auto ES = [&](int slot, int e) { return (slot * 4 + e) * SW + l; };
@@ -654,39 +662,84 @@ __device__ __forceinline__ void stream_solve(const KParams &p, int k, int s, int
         lk[(((s + 1) & 1) * 2 + 1) * SW + l] = u[LC - 1];
     }
     __syncthreads();
+    const int t = s - 1 - k;
+    const int g = t * ST + c;  // the chunk's index along the column (or window)
+    double *cPk = cPr + k * R * SW;
     // the chunk's own recurrences enter the derivative only as y + z
     double w[LC], Pc, Bc;
     {
+        double um2 = edge[ES(c, 2)], um1 = edge[ES(c, 3)], up0 = edge[ES(c + 2, 0)],
+               up1 = edge[ES(c + 2, 1)];
+        if (wall && g == 0) {
+            um2 = par * u[1];
+            um1 = par * u[0];
+        }
+        if (wall && g == nc - 1) {
+            up0 = par * u[LC - 1];
+            up1 = par * u[LC - 2];
+        }
         double y[LC], z[LC];
-        iir_chunk<LC>(p, u, edge[ES(c, 2)], edge[ES(c, 3)], edge[ES(c + 2, 0)],
-                      edge[ES(c + 2, 1)], y, z, Pc, Bc);
+        iir_chunk<LC>(p, u, um2, um1, up0, up1, y, z, Pc, Bc);
 #pragma unroll
-        for (int k = 0; k < LC; ++k) w[k] = y[k] + z[k];
+        for (int j = 0; j < LC; ++j) w[j] = y[j] + z[j];
     }
-    // the chunk's index in the window, offset to stay positive in the first
-    // steps (whose tiles lie before the window)
-    const int v = (s - 1 - k) * ST + c + 4 * R;
-    double *cPk = cPr + k * R * SW;
-    cPk[(v & (R - 1)) * SW + l] = Pc;
+    // ring slot of chunk i: (i + 4 R) & (R - 1), positive in the first steps
+    // (whose tiles lie before the column)
+    cPk[((g + 4 * R) & (R - 1)) * SW + l] = Pc;
     cB[c * SW + l] = Bc;
     if (c < MC) {
-        // the anti-causal carry of the next tile's chunk c
+        // the carries of the next tile's chunk c
+        double vp0 = edge[ES(ST + 2 + c, 0)], vp1 = edge[ES(ST + 2 + c, 1)];
+        if (wall && g + ST == nc - 1) {
+            vp0 = par * un[LC - 1];
+            vp1 = par * un[LC - 2];
+        }
         double y2[LC], z2[LC], P2, B2;
-        iir_chunk<LC>(p, un, edge[ES(ST + c, 2)], edge[ES(ST + c, 3)], edge[ES(ST + 2 + c, 0)],
-                      edge[ES(ST + 2 + c, 1)], y2, z2, P2, B2);
+        iir_chunk<LC>(p, un, edge[ES(ST + c, 2)], edge[ES(ST + c, 3)], vp0, vp1, y2, z2, P2, B2);
         cB[(ST + c) * SW + l] = B2;
+        lookP[c * SW + l] = P2;
     }
     __syncthreads();
     const double qL = p.iir_qL_col;
     double Yc = 0.0, Zc = 0.0;
+    // only the first tile and the tiles within MC chunks of the last wall
+    // meet images (the same for the whole block)
+    if (!wall || (t > 0 && (t + 1) * ST + MC <= nc)) {
 #pragma unroll
-    for (int mm = MC; mm >= 1; --mm) {
-        Yc = Yc * qL + cPk[((v - mm) & (R - 1)) * SW + l];
-        Zc = Zc * qL + cB[(c + mm) * SW + l];
+        for (int mm = MC; mm >= 1; --mm) {
+            Yc = Yc * qL + cPk[((g - mm + 4 * R) & (R - 1)) * SW + l];
+            Zc = Zc * qL + cB[(c + mm) * SW + l];
+        }
+#pragma unroll
+        for (int j = 0; j < LC; ++j)
+            d[j] = p.iir_K * (w[j] + (p.iir_qp[j + 1] * Yc + p.iir_qp[LC - 1 - j] * Zc));
+        return;
     }
 #pragma unroll
-    for (int k = 0; k < LC; ++k)
-        d[k] = p.iir_K * (w[k] + (p.iir_qp[k + 1] * Yc + p.iir_qp[LC - 1 - k] * Zc));
+    for (int mm = MC; mm >= 1; --mm) {
+        const int gp = g - mm, gq = g + mm;
+        double cp, cb;
+        if (wall && gp < 0) {
+            // image of chunk -1 - gp, in the first tile
+            cp = -par * p.iir_inv_q * cB[(-1 - gp) * SW + l];
+        } else {
+            cp = cPk[((gp + 4 * R) & (R - 1)) * SW + l];
+        }
+        if (wall && gq >= nc) {
+            // image of chunk h, in this tile, the one before or the next
+            const int h = 2 * nc - 1 - gq;
+            const double ph = h >= (t + 1) * ST ? lookP[(h - (t + 1) * ST) * SW + l]
+                                                : cPk[((h + 4 * R) & (R - 1)) * SW + l];
+            cb = -par * p.iir_q * ph;
+        } else {
+            cb = cB[(c + mm) * SW + l];
+        }
+        Yc = Yc * qL + cp;
+        Zc = Zc * qL + cb;
+    }
+#pragma unroll
+    for (int j = 0; j < LC; ++j)
+        d[j] = p.iir_K * (w[j] + (p.iir_qp[j + 1] * Yc + p.iir_qp[LC - 1 - j] * Zc));
 }
 
 template <int SW, int ST, int LC>
@@ -696,17 +749,24 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
                                                             double *__restrict__ mu_out,
                                                             double *__restrict__ fy_out)
 {
-    constexpr int E = kColWin<LC>;
     using S = StreamLds<SW, ST, LC>;
     extern __shared__ double smem[];
     double *edge = smem, *cPr = edge + S::NE * 4 * SW, *cB = cPr + 3 * S::R * SW,
-           *left = cB + (ST + S::MC) * SW;
+           *left = cB + (ST + S::MC) * SW, *lookP = left + 3 * 4 * SW;
     // the carries and edges of chunks before the window start from zero
     for (int i = threadIdx.x; i < S::doubles; i += SW * ST) smem[i] = 0.0;
     const int nx = p.nx, ny = p.ny;
     const int c = threadIdx.x / SW, l = threadIdx.x - c * SW;
     const int col = blockIdx.x * SW + l;  // nx is a multiple of SW
+    // between walls the solves close at the walls with mirror images and
+    // take the column alone; periodic columns take the window of kColWin
+    // chunks past each end
+    const bool wall = p.bc_y != 0;
+    const int E = wall ? 0 : kColWin<LC>;
     const int nc = ny / LC, NV = nc + 2 * E, ntile = (NV + ST - 1) / ST;
+    // parities of the solves' inputs about a wall: rho even, d/dy rho odd, mu
+    // even (mu - mu_wall odd for wetting walls)
+    const double par2 = p.wet ? -1.0 : 1.0;
     // the LC values of window chunk v (zero outside the window): its rows
     // run down from the first one, or up beyond a wall (the mirror image)
     auto load = [&](const double *__restrict__ src, int v, double (&o)[LC]) {
@@ -746,7 +806,8 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
         load(mux, (s - 2) * ST + c, mx);
         double d1[LC];
         if (run0) {
-            stream_solve<SW, ST, LC>(p, 0, s, c, l, r1, rn, edge, cPr, cB, left, d1);
+            stream_solve<SW, ST, LC>(p, 0, s, c, l, nc, wall, 1.0, r1, rn, edge, cPr, cB, left,
+                                     lookP, d1);
         } else {
 #pragma unroll
             for (int k = 0; k < LC; ++k) d1[k] = 0.0;
@@ -756,7 +817,8 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
         {
             double d2[LC];
             if (run1) {
-                stream_solve<SW, ST, LC>(p, 1, s, c, l, a1, d1, edge, cPr, cB, left, d2);
+                stream_solve<SW, ST, LC>(p, 1, s, c, l, nc, wall, -1.0, a1, d1, edge, cPr, cB,
+                                         left, lookP, d2);
             } else {
 #pragma unroll
                 for (int k = 0; k < LC; ++k) d2[k] = 0.0;
@@ -778,7 +840,8 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
         }
         double d3[LC];
         if (run2) {
-            stream_solve<SW, ST, LC>(p, 2, s, c, l, m3, mw, edge, cPr, cB, left, d3);
+            stream_solve<SW, ST, LC>(p, 2, s, c, l, nc, wall, par2, m3, mw, edge, cPr, cB, left,
+                                     lookP, d3);
         } else {
 #pragma unroll
             for (int k = 0; k < LC; ++k) d3[k] = 0.0;
@@ -1450,8 +1513,10 @@ bool col_stream_ok(const KParams &p, int width)
 {
     const int lc = col_stream_chunk(p.ny);
     const int win = lc == 8 ? kColWin<8> * 8 : kColWin<4> * 4;
+    // between walls the solves close with mirror images; periodic columns
+    // need the window, which must not wrap more than once
     return !p.sc && (width == 8 || width == 16 || width == 32) && p.nx % width == 0 &&
-           p.ny % 4 == 0 && p.ny >= win && p.ny >= kFastMinLine;
+           p.ny % 4 == 0 && p.ny >= kFastMinLine && (p.bc_y || p.ny >= win);
 }
 
 hipError_t launch_cols_mu_iir(const KParams &p, const double *rho, const double *mux, double *mu,

@@ -519,31 +519,36 @@ def test_full_size_1000_steps(name, golden_dir):
     assert er <= TOL and ev <= TOL
 
 
-@pytest.mark.parametrize("case", ["periodic16_lc4", "periodic16_lc8", "walls_wetting16",
-                                  "kappa0_walls8", "walls32_shortest4", "walls16_shortest8"])
+STREAM_CASES = {
+    # name: (nx, ny, width, extra params)
+    "periodic16_lc4": (32, 1004, 16, {}),
+    "periodic16_lc8": (32, 1000, 16, {}),
+    "periodic32_shortest4": (64, 148, 32, {}),
+    "periodic16_shortest8": (32, 168, 16, {}),
+    "walls_wetting16": (48, 2048, 16, dict(bc_y=1, wetting=1, mu_wall=-0.05)),
+    "kappa0_walls8": (16, 600, 8, dict(bc_y=1)),
+    "walls32_short4": (64, 68, 32, dict(bc_y=1)),
+    "walls16_short8": (32, 64, 16, dict(bc_y=1)),
+    "walls_ragged16": (32, 784, 16, dict(bc_y=1)),
+    "walls_wetting_lookahead16": (32, 800, 16, dict(bc_y=1, wetting=1, mu_wall=0.03)),
+}
+
+
+@pytest.mark.parametrize("case", list(STREAM_CASES))
 def test_column_stream_matches_oracle(case):
     """The column pass streamed down strips (lbm_set_column_shape with chunk
-    LBM_COLUMN_STREAM; 8-node chunks where ny is a multiple of 8, else 4):
-    periodic columns of 1004 (4-node chunks) and 1000 nodes (8-node), 16
-    wide, the last tile ragged; 2048-node columns between wetting walls, 16
-    wide (mu - mu_wall odd beyond the walls); kappa = 0 between walls, 8 wide
-    (one derivative before mu); the shortest columns whose windows reflect
-    once between walls: 148 nodes 32 wide (4-node chunks, 144-row windows)
-    and 168 nodes 16 wide (8-node, 168).  Parity with the oracle after 40
-    steps, and the whole-column shape agrees to round-off."""
-    kw = dict()
-    if case == "periodic16_lc4":
-        nx, ny, width = 32, 1004, 16
-    elif case == "periodic16_lc8":
-        nx, ny, width = 32, 1000, 16
-    elif case == "walls_wetting16":
-        nx, ny, width, kw = 48, 2048, 16, dict(bc_y=1, wetting=1, mu_wall=-0.05)
-    elif case == "kappa0_walls8":
-        nx, ny, width, kw = 16, 600, 8, dict(bc_y=1)
-    elif case == "walls32_shortest4":
-        nx, ny, width, kw = 64, 148, 32, dict(bc_y=1)
-    else:
-        nx, ny, width, kw = 32, 168, 16, dict(bc_y=1)
+    LBM_COLUMN_STREAM; 8-node chunks where ny is a multiple of 8, else 4).
+    Periodic columns take windows past both ends: 1004 and 1000 nodes (4- and
+    8-node chunks, the last tile ragged) and the shortest the windows allow
+    (148 and 168 nodes).  Between walls the solves close with mirror images:
+    2048 nodes between wetting walls (mu - mu_wall odd); kappa = 0 (one
+    derivative before mu); 68 and 64 nodes (a single tile, chunks near both
+    walls); 784 nodes (the last tile holds 2 chunks: the images after the wall
+    take their carries from the tile before); 800 nodes between wetting walls
+    (the wall 4 chunks into the next tile: the images take the look-ahead
+    chunks' carries).  Parity with the oracle after 40 steps, and the
+    whole-column shape agrees to round-off."""
+    nx, ny, width, kw = STREAM_CASES[case]
     kappa = 0.0 if case == "kappa0_walls8" else 0.1
     p, op = _case_params(lbm.EOS_CS, 0.7, nx, ny, kappa=kappa, tau=0.8, k=0.2, mu_cap=6.0,
                          **kw)
@@ -570,13 +575,15 @@ def test_column_stream_matches_oracle(case):
 
 
 def test_column_stream_rejects_what_it_cannot_take():
-    """Streamed strips need nx a multiple of the width, ny a multiple of 4 at
-    least as long as the window (144 rows with 4-node chunks, 168 with 8-node
-    chunks where ny is a multiple of 8), and the chemical-potential force."""
+    """Streamed strips need nx a multiple of the width, ny a multiple of 4 of
+    at least 64 nodes and, for periodic columns, at least as long as the
+    window (144 rows with 4-node chunks, 168 with 8-node chunks where ny is a
+    multiple of 8), and the chemical-potential force."""
     cases = [(lbm.EOS_CS, 40, 256, 16, {}),          # nx not a multiple of 16
              (lbm.EOS_CS, 64, 140, 16, {}),          # shorter than the 144-row window
              (lbm.EOS_CS, 64, 160, 16, {}),          # shorter than the 168-row window
              (lbm.EOS_CS, 64, 150, 16, {}),          # ny not a multiple of 4
+             (lbm.EOS_CS, 64, 60, 16, dict(bc_y=1)),  # shorter than 64 between walls
              (lbm.EOS_CS, 64, 256, 4, {}),           # width
              (lbm.EOS_CS, 64, 256, 16, dict(force=lbm.FORCE_SC))]
     for eos, nx, ny, width, kw in cases:
