@@ -256,17 +256,21 @@ lbm_status lbm_set_collision_variant(lbm_ctx *ctx, int variant);
  * above and below it (M the carries of the factorised solve: 11, 6, 3) --
  * mirrored about a wall -- so that strips stay wide on long columns (the
  * default for columns of more than 4096 nodes: width 4, chunk 8; tiles of
- * 1712 rows); it needs columns of more than one tile.  chunk =
+ * 1712 rows, where the streamed strips below do not apply); it needs
+ * columns of more than one tile.  chunk =
  * LBM_COLUMN_STREAM (width 8, 16 or 32) streams each strip down the columns:
  * one workgroup per strip (512 threads) walks down it in tiles of chunks (8
  * nodes where ny is a multiple of 8, else 4), its three chained derivatives
  * pipelined one tile apart, so that each row of a plane is read and written
- * in whole strip-wide pieces (16 columns: one 128-byte line) and, apart from
- * windows above and below the column (168 rows with 8-node chunks, 144 with
- * 4), once; it needs nx a multiple of the width, ny a multiple of 4 and at
- * least as long as the window, and the chemical-potential force (not the
- * pseudopotential model).  LBM_E_INVALID if the shape does not fit.  Results
- * of every shape agree to round-off. */
+ * in whole strip-wide pieces (16 columns: one 128-byte line) and once --
+ * between walls each solve closes with the mirror image's edge values and
+ * carries; periodic columns add windows above and below (168 rows with
+ * 8-node chunks, 144 with 4); it needs nx a multiple of the width, ny a
+ * multiple of 4 of at least 64 nodes (periodic: at least the window), and the
+ * chemical-potential force (not the pseudopotential model); the default,
+ * 16 wide, for meshes of at least
+ * 4096 x 2048 nodes.  LBM_E_INVALID if the shape does not fit.  Results of
+ * every shape agree to round-off. */
 #define LBM_COLUMN_STREAM 1
 lbm_status lbm_set_column_shape(lbm_ctx *ctx, int width, int chunk);
 

@@ -214,6 +214,13 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     set_row_shape(&k);
     k.row_keep = 1;
     set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
+    // wide meshes with long columns: 16-column strips streamed down the
+    // columns (at 4096 x 2048 and 16384 x 8192 they take half the time of
+    // whole-column strips or tiles; the autotuner decides elsewhere)
+    if (k.nx >= 4096 && k.ny >= 2048 && set_col_stream(&k, 16)) {
+        *kp = k;
+        return true;
+    }
     // columns longer than one workgroup's reduction holds: tiles with
     // windows, 4 columns wide
     if (k.ny > kMaxLine && !set_col_tiles(&k, kDefaultStripWidth, 8)) {
