@@ -213,6 +213,9 @@ bool make_kparams(const lbm_params *p, KParams *kp, std::string *why)
     }
     set_row_shape(&k);
     k.row_keep = 1;
+    // planes f[9][ny][nx] (the layout of lbm_get_state); a context switches
+    // to rows interleaved
+    set_state_layout(&k, false);
     set_col_shape(&k, kDefaultStripWidth, kDefaultChunk);
     // wide meshes with long columns: 16-column strips streamed down the
     // columns (at 4096 x 2048 and 16384 x 8192 they take half the time of
@@ -369,6 +372,28 @@ lbm_status copy_out(lbm_ctx *c, double *dst, const double *src, size_t n, int on
     return LBM_OK;
 }
 
+// Copy a state between planes f[9][ny][nx] (the layout of lbm_get_state) and
+// the context's layout (to_planes: from the context into planes).
+lbm_status copy_state(lbm_ctx *c, double *dst, const double *src, bool to_planes,
+                      hipMemcpyKind kind)
+{
+    const size_t nx = c->kp.nx, ny = c->kp.ny, N = nx * ny, row = nx * sizeof(double);
+    if (c->kp.fq == N) {
+        HIP_OR(c, hipMemcpyAsync(dst, src, 9 * N * sizeof(double), kind, c->stream));
+        return LBM_OK;
+    }
+    const size_t pitch = c->kp.fr * sizeof(double);
+    for (int q = 0; q < 9; ++q) {
+        if (to_planes)
+            HIP_OR(c, hipMemcpy2DAsync(dst + q * N, row, src + q * c->kp.fq, pitch, row, ny, kind,
+                                       c->stream));
+        else
+            HIP_OR(c, hipMemcpy2DAsync(dst + q * c->kp.fq, pitch, src + q * N, row, row, ny, kind,
+                                       c->stream));
+    }
+    return LBM_OK;
+}
+
 // Collision pass variant (fast rows only): 0 one pass reading f twice,
 // 1 one pass holding f in registers (rows of up to 1024 nodes), 2 one pass
 // over row segments holding f in registers, F_x from a window around each
@@ -514,6 +539,9 @@ lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, 
     if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
     c->prm = *p;
     c->kp = kp;
+    // each row's nine populations side by side: every pass then reads and
+    // writes one contiguous block per row instead of nine planes far apart
+    set_state_layout(&c->kp, true);
     c->N = N;
     c->stream = (hipStream_t)hip_stream;
     c->red_blocks = rho_delta_blocks(kp);
@@ -560,8 +588,8 @@ lbm_status lbm_init(const lbm_params *p, const double *rho0, const double *ux0, 
             d_uy = c->obs + 2 * N;
         }
     }
-    if (e == hipSuccess) e = launch_init_feq(kp, d_rho, d_ux, d_uy, c->f[0], c->stream);
-    if (e == hipSuccess) e = launch_density_groups(kp, c->f[0], c->g[0], c->stream);
+    if (e == hipSuccess) e = launch_init_feq(c->kp, d_rho, d_ux, d_uy, c->f[0], c->stream);
+    if (e == hipSuccess) e = launch_density_groups(c->kp, c->f[0], c->g[0], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         std::string m = std::string("initialisation on the device failed: ") + hipGetErrorString(e);
@@ -656,7 +684,10 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f, int dst_on_device)
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
     if (!f) return fail(c, LBM_E_INVALID, "f is NULL");
-    if ((st = copy_out(c, f, c->f[c->cur], 9 * c->N, dst_on_device)) != LBM_OK) return st;
+    if ((st = copy_state(c, f, c->f[c->cur], true,
+                         dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost)) !=
+        LBM_OK)
+        return st;
     HIP_OR(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -666,9 +697,10 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int src_on_device)
     lbm_status st = enter(c);
     if (st != LBM_OK) return st;
     if (!f) return fail(c, LBM_E_INVALID, "f is NULL");
-    HIP_OR(c, hipMemcpyAsync(c->f[c->cur], f, 9 * c->N * sizeof(double),
-                             src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                             c->stream));
+    if ((st = copy_state(c, c->f[c->cur], f, false,
+                         src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)) !=
+        LBM_OK)
+        return st;
     HIP_OR(c, launch_density_groups(c->kp, c->f[c->cur], c->g[c->cur], c->stream));
     HIP_OR(c, hipStreamSynchronize(c->stream));
     return LBM_OK;

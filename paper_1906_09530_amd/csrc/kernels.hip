@@ -152,7 +152,6 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
 {
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
-    const size_t N = (size_t)nx * ny;
     const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
     double *bA = smem, *bB = smem + p.rows_per_block * nx;
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(MAXT) void k_rows_rho(KParams p,
         if (!E.ok[k]) continue;
         const size_t node = (size_t)(y0 + E.l[k]) * nx + E.j[k];
         double fi[9];
-        load9(f, N, node, fi);
+        load9(f, p.fq, (size_t)(y0 + E.l[k]) * p.fr + E.j[k], fi);
         const double r = sum9(fi);
         rr[k] = r;
         bA[E.e[k]] = r;
@@ -275,7 +274,6 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
 {
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
-    const size_t N = (size_t)nx * ny;
     const int y0 = blockIdx.x * p.rows_per_block;
     const int rows = min(p.rows_per_block, ny - y0);
     double *bA = smem, *bB = smem + p.rows_per_block * nx;
@@ -288,7 +286,7 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
     for (int k = 0; k < kElemsPerThread; ++k) {
         if (!E.ok[k]) continue;
         double (&q)[9] = fi[KEEP ? k : 0];
-        load9(f, N, (size_t)(y0 + E.l[k]) * nx + E.j[k], q);
+        load9(f, p.fq, (size_t)(y0 + E.l[k]) * p.fr + E.j[k], q);
         rho[k] = sum9(q);
         bA[E.e[k]] = rho[k];
     }
@@ -312,7 +310,7 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
         const int x = E.j[k], y = y0 + E.l[k];
         const size_t node = (size_t)y * nx + x;
         double (&q)[9] = fi[KEEP ? k : 0];
-        if (!KEEP) load9(f, N, node, q);
+        if (!KEEP) load9(f, p.fq, (size_t)y * p.fr + x, q);
         const double rh = rho[k];
         const double jx = (q[1] - q[3]) + (q[5] - q[6]) + (q[8] - q[7]);
         const double jy = (q[2] - q[4]) + (q[5] - q[8]) + (q[6] - q[7]);
@@ -345,12 +343,12 @@ __global__ __launch_bounds__(MAXT) void k_rows_collide(
                 if (p.bc_y) {
                     // half-way bounce-back; a moving wall adds -2 w rho (e.U)/c_s^2
                     const double eu = EX[i] * p.wall_ux;
-                    fout[OPP[i] * N + node] = fs - 2.0 * WT[i] * rh * eu / CS2;
+                    fout[OPP[i] * p.fq + (size_t)y * p.fr + x] = fs - 2.0 * WT[i] * rh * eu / CS2;
                     continue;
                 }
                 ty = ty < 0 ? ty + ny : ty - ny;
             }
-            fout[i * N + (size_t)ty * nx + tx] = fs;
+            fout[i * p.fq + (size_t)ty * p.fr + tx] = fs;
         }
     }
 }
@@ -363,20 +361,25 @@ __global__ void k_init_feq(KParams p, const double *__restrict__ rho0,
          n += (size_t)gridDim.x * blockDim.x) {
         const double rho = rho0[n], ux = ux0 ? ux0[n] : 0.0, uy = uy0 ? uy0[n] : 0.0;
         const double uu = ux * ux + uy * uy;
+        const size_t y = n / p.nx, o = y * p.fr + (n - y * p.nx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i * N + n] = feq(i, rho, ux, uy, uu);
+        for (int i = 0; i < 9; ++i) f[i * p.fq + o] = feq(i, rho, ux, uy, uu);
     }
 }
 
 // The three density groups of a state f, in the order the collision pass
 // sums them: g0 = (f0 + f1) + f3, g1 = (f2 + f5) + f6, g2 = (f4 + f7) + f8.
-__global__ void k_density_groups(size_t N, const double *__restrict__ f, double *__restrict__ g)
+__global__ void k_density_groups(KParams p, const double *__restrict__ f, double *__restrict__ g)
 {
+    const size_t N = (size_t)p.nx * p.ny, F = p.fq, G = p.gq;
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x) {
-        g[n] = (f[n] + f[N + n]) + f[3 * N + n];
-        g[N + n] = (f[2 * N + n] + f[5 * N + n]) + f[6 * N + n];
-        g[2 * N + n] = (f[4 * N + n] + f[7 * N + n]) + f[8 * N + n];
+        const size_t y = n / p.nx, x = n - y * p.nx;
+        const double *q = f + y * p.fr + x;
+        double *h = g + y * p.gr + x;
+        h[0] = (q[0] + q[F]) + q[3 * F];
+        h[G] = (q[2 * F] + q[5 * F]) + q[6 * F];
+        h[2 * G] = (q[4 * F] + q[7 * F]) + q[8 * F];
     }
 }
 
@@ -392,7 +395,8 @@ __global__ __launch_bounds__(kRedThreads) void k_rho_delta(KParams p, const doub
     for (size_t n = blockIdx.x * (size_t)blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x) {
         double fi[9];
-        load9(f, N, n, fi);
+        const size_t y = n / p.nx;
+        load9(f, p.fq, y * p.fr + (n - y * p.nx), fi);
         const double r = sum9(fi);
         if (!isfinite(r)) bad = 1.0;
         const double d = fabs(r - prev[n]);
@@ -540,6 +544,15 @@ bool set_col_tiles(KParams *p, int width, int chunk)
     return true;
 }
 
+void set_state_layout(KParams *p, bool rows_interleaved)
+{
+    const size_t nx = p->nx, N = nx * p->ny;
+    p->fq = rows_interleaved ? nx : N;
+    p->fr = rows_interleaved ? 9 * nx : nx;
+    p->gq = rows_interleaved ? nx : N;
+    p->gr = rows_interleaved ? 3 * nx : nx;
+}
+
 bool set_col_stream(KParams *p, int width)
 {
     if (!col_stream_ok(*p, width)) return false;
@@ -671,7 +684,7 @@ hipError_t launch_density_groups(const KParams &p, const double *f, double *g, h
     const size_t N = (size_t)p.nx * p.ny;
     int blocks = (int)((N + 255) / 256);
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_density_groups, dim3(blocks), dim3(256), 0, s, N, f, g);
+    hipLaunchKernelGGL(k_density_groups, dim3(blocks), dim3(256), 0, s, p, f, g);
     return hipGetLastError();
 }
 

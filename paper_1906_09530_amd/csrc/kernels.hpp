@@ -53,7 +53,16 @@ struct KParams {
     int iir_m_row, iir_m_col;
     double iir_q, iir_inv_q, iir_K, iir_qL_row, iir_qL_col;
     double iir_qp[17];
+    // layout of the distribution f and of its density groups g: population
+    // (group) i of node (x, y) at f[i fq + y fr + x] (g[i gq + y gr + x]);
+    // planes (fq = nx ny, fr = nx) or each row's populations side by side
+    // (fq = nx, fr = 9 nx; gq = nx, gr = 3 nx)
+    size_t fq, fr, gq, gr;
 };
+
+// Plane-major (f[9][ny][nx], g[3][ny][nx]) or row-interleaved
+// (f[ny][9][nx], g[ny][3][nx]) layout of the state.
+void set_state_layout(KParams *p, bool rows_interleaved);
 
 constexpr int kIirRowChunk = 4;
 // row segment of the segment kernels: 224 chunks, which with the collision
@@ -64,7 +73,7 @@ constexpr int kMaxWholeRow = 4096;    // longest row one workgroup holds
 int row_blocks(const KParams &p);
 int col_blocks(const KParams &p);
 
-// The state is f together with its three density groups g (3 planes of N):
+// The state is f together with its three density groups g (layout: KParams fq..gr):
 // at each node g0 = (f0 + f1) + f3, g1 = (f2 + f5) + f6, g2 = (f4 + f7) + f8,
 // so that rho = (g0 + g1) + g2.  The collision pass writes g with the new f;
 // wherever f is set otherwise, launch_density_groups forms them.

@@ -335,17 +335,17 @@ __device__ __forceinline__ void rows_rho_body(const KParams &p, int y0, const do
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
-    const size_t N = (size_t)nx * ny;
     const int rows = min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = row_chunk<LC>(p, rows);
     const LineLds L = carve_lds(smem, m);
     const size_t base = (size_t)(y0 + m.l) * nx + m.c * LC;
+    const size_t gb = (size_t)(y0 + m.l) * p.gr + m.c * LC;
     double rho[LC];
     if (m.ok) {
         double g0[LC], g1[LC], g2[LC];
-        vload<LC>(g + base, g0);
-        vload<LC>(g + N + base, g1);
-        vload<LC>(g + 2 * N + base, g2);
+        vload<LC>(g + gb, g0);
+        vload<LC>(g + p.gq + gb, g1);
+        vload<LC>(g + 2 * p.gq + gb, g2);
 #pragma unroll
         for (int k = 0; k < LC; ++k) rho[k] = (g0[k] + g1[k]) + g2[k];
         vstore<LC>(rho_out + base, rho);
@@ -871,7 +871,7 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
 // more waves per SIMD; the second read is served by the caches).
 //
 // Besides the new state fout, the pass writes its three density groups gout
-// (planes of N): with f the streamed populations at a node,
+// (in the layout KParams gives): with f the streamed populations at a node,
 //   g0 = (f0 + f1) + f3,   g1 = (f2 + f5) + f6,   g2 = (f4 + f7) + f8,
 // the populations that arrive from the same row, from the row below and from
 // the row above.  The next pass A forms rho = (g0 + g1) + g2 from them and so
@@ -898,7 +898,6 @@ __device__ __forceinline__ void rows_collide_body(
     constexpr int LC = kRowLC;
     extern __shared__ double smem[];
     const int nx = p.nx, ny = p.ny;
-    const size_t N = (size_t)nx * ny;
     const int rows = SEG ? 1 : min(p.rows_per_block, ny - y0);
     const Chunk<LC> m = SEG ? seg_chunk<LC>(p, seg_n) : row_chunk<LC>(p, rows);
     // SEG: the window's chunks; LDS holds the window solve (edges, carries)
@@ -916,7 +915,9 @@ __device__ __forceinline__ void rows_collide_body(
     }
     const int xc = xs + m.c * LC;
     const int y = y0 + m.l, x0 = !SEG ? xc : (xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc));
-    const size_t base = (size_t)y * nx + x0;
+    // node (x0, y) in the scalar planes, in f and in g
+    const size_t base = (size_t)y * nx + x0, fb = (size_t)y * p.fr + x0,
+                 gb = (size_t)y * p.gr + x0;
     constexpr int NI = KEEP ? 9 : 1;
     double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
     if (m.ok) {
@@ -927,7 +928,7 @@ __device__ __forceinline__ void rows_collide_body(
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             double t[LC];
-            vload<LC>(f + i * N + base, t);
+            vload<LC>(f + i * p.fq + fb, t);
 #pragma unroll
             for (int k = 0; k < LC; ++k) {
                 if (KEEP) fi[i][k] = t[k];
@@ -1028,7 +1029,7 @@ __device__ __forceinline__ void rows_collide_body(
 #pragma unroll
                     for (int k = 0; k < LC; ++k) qa[i][k] = fi[KEEP ? i : 0][k];
                 } else {
-                    vload<LC>(f + i * N + base, qa[i]);
+                    vload<LC>(f + i * p.fq + fb, qa[i]);
                 }
             }
 #pragma unroll
@@ -1048,7 +1049,7 @@ __device__ __forceinline__ void rows_collide_body(
 #pragma unroll
                 for (int k = 0; k < LC; ++k) q[k] = fi[KEEP ? i : 0][k];
             } else {
-                vload<LC>(f + i * N + base, q);
+                vload<LC>(f + i * p.fq + fb, q);
             }
 #pragma unroll
             for (int k = 0; k < LC; ++k) {
@@ -1140,12 +1141,12 @@ __device__ __forceinline__ void rows_collide_body(
             }
             if (!store) continue;
             if (refl) {
-                vstore<LC>(fout + OPP[i] * N + base, v);
+                vstore<LC>(fout + OPP[i] * p.fq + fb, v);
                 continue;
             }
             int ty = y + EY[i];
             ty = ty < 0 ? ty + ny : (ty >= ny ? ty - ny : ty);
-            double *dst = fout + i * N + (size_t)ty * nx;
+            double *dst = fout + i * p.fq + (size_t)ty * p.fr;
             if (EX[i] == 0) {
                 vstore<LC>(dst + x0, v);
                 continue;
@@ -1215,9 +1216,11 @@ __device__ __forceinline__ void rows_collide_body(
     }
     // g0 of this row; g1 of the row above (of this row at a top wall, as
     // g2); g2 of the row below (of this row at a bottom wall, as g1)
-    const size_t up = refl_u ? 2 * N + base : N + (size_t)(y + 1 < ny ? y + 1 : 0) * nx + x0;
-    const size_t dn = refl_d ? N + base : 2 * N + (size_t)(y > 0 ? y - 1 : ny - 1) * nx + x0;
-    vstore<LC>(gout + base, gm);
+    const size_t up =
+        refl_u ? 2 * p.gq + gb : p.gq + (size_t)(y + 1 < ny ? y + 1 : 0) * p.gr + x0;
+    const size_t dn =
+        refl_d ? p.gq + gb : 2 * p.gq + (size_t)(y > 0 ? y - 1 : ny - 1) * p.gr + x0;
+    vstore<LC>(gout + gb, gm);
     vstore<LC>(gout + up, gu);
     vstore<LC>(gout + dn, gd);
 }
@@ -1286,18 +1289,17 @@ __global__ __launch_bounds__(kRhoThreads) void k_rows_rho_seg_iir(KParams p,
     const int y = blockIdx.x / nseg, sg = blockIdx.x - y * nseg;
     const int xs = sg * kRhoSegLen, nc = min(kRhoSegLen, p.nx - xs) / LC;
     const int nx = p.nx, w = threadIdx.x, nw = nc + 2 * kRhoWin, c = w - kRhoWin;
-    const size_t N = (size_t)nx * p.ny;
     const int xc = xs + c * LC;
     const int x0 = xc < 0 ? xc + nx : (xc >= nx ? xc - nx : xc);
-    const size_t base = (size_t)y * nx + x0;
+    const size_t base = (size_t)y * nx + x0, gb = (size_t)y * p.gr + x0;
     const bool core = c >= 0 && c < nc;
     double *vbuf = smem, *cP = smem + 4 * nw, *cB = cP + nw;
     double rho[LC], mx[LC];
     if (w < nw) {
         double g0[LC], g1[LC], g2[LC];
-        vload<LC>(g + base, g0);
-        vload<LC>(g + N + base, g1);
-        vload<LC>(g + 2 * N + base, g2);
+        vload<LC>(g + gb, g0);
+        vload<LC>(g + p.gq + gb, g1);
+        vload<LC>(g + 2 * p.gq + gb, g2);
 #pragma unroll
         for (int k = 0; k < LC; ++k) rho[k] = (g0[k] + g1[k]) + g2[k];
         if (core) {

@@ -25,11 +25,13 @@ __device__ __forceinline__ double sum9(const double (&fi)[9])
     return r;
 }
 
-__device__ __forceinline__ void load9(const double *__restrict__ f, size_t N, size_t node,
+// The nine populations at offset `node` of a state whose planes lie `stride`
+// apart.
+__device__ __forceinline__ void load9(const double *__restrict__ f, size_t stride, size_t node,
                                       double (&fi)[9])
 {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fi[i] = f[i * N + node];
+    for (int i = 0; i < 9; ++i) fi[i] = f[i * stride + node];
 }
 
 // Equilibrium of Eq. 2 with c_s^2 = 1/3.
