@@ -5,9 +5,12 @@ velocity); the converged states become training samples of the network of
 include/lbm_warmstart.h, which the library trains with its own FP32 kernels;
 the trained network then proposes the initial density and velocity of new
 drops (BF16 inference, density mass matched to the tanh start), and both
-starts are run to the same convergence criterion.  Every numerical step
-(solver, training, inference, warm-start fields) runs in the library's
-kernels; this module only draws the workload, assembles the samples and
+starts are run to the same convergence criterion.  The solver, the
+training, the inference and the warm-start fields run in the library's
+kernels; this module draws the workload, forms the training samples on the
+host from the converged fields (seven normalised features per sampled node,
+and as targets the normalised log density and the radial and azimuthal
+velocity: a few elementwise numpy operations on every second node) and
 keeps the books.
 
 Workloads (square periodic meshes; T/Tc, radius fraction and k drawn per
