@@ -20,9 +20,11 @@
  * (Eq. 25) and enters only as the factor k^2 of Eq. 33.
  *
  * Layout: a scalar field is nx*ny doubles, row-major, node (x, y) at index
- * y*nx + x.  The distribution state is 9 such planes, f[i][y][x], with the
- * D2Q9 velocities e_0..e_8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
- * (-1,-1),(1,-1) (Sec. 2).  The stored state is the pre-collision f(t).
+ * y*nx + x.  The distribution state at the ABI is 9 such planes, f[i][y][x],
+ * with the D2Q9 velocities e_0..e_8 = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),
+ * (-1,1),(-1,-1),(1,-1) (Sec. 2).  The stored state is the pre-collision
+ * f(t).  (A context keeps each row's nine populations side by side on the
+ * device, f[y][i][x]; lbm_get_state and lbm_set_state convert.)
  *
  * Boundaries: x is periodic.  y is periodic (bc_y = 0) or closed by
  * half-way bounce-back walls at y = -1/2 and y = ny - 1/2 (bc_y = 1) that may
@@ -180,7 +182,8 @@ lbm_status lbm_run_until_converged(lbm_ctx *ctx, double tol, int64_t check_every
                                    int64_t max_steps, int64_t *steps_done, double *last_delta);
 
 /* Copy the state f[9][ny][nx] out of / into the context (checkpoint and
- * resume; resuming reproduces a run bit for bit). */
+ * resume; resuming reproduces a run bit for bit), converting from / to the
+ * context's row-interleaved layout with one strided copy per population. */
 lbm_status lbm_get_state(lbm_ctx *ctx, double *f, int dst_on_device);
 lbm_status lbm_set_state(lbm_ctx *ctx, const double *f, int src_on_device);
 
