@@ -1247,6 +1247,8 @@ lbm_status lbm_batch_create(int32_t nsims, const lbm_params *params, const doubl
         if (p->nx < 64 || p->ny < 64 || p->nx > 1024 || p->ny > 1024 || p->nx % 8 || p->ny % 8)
             return give_up(LBM_E_INVALID, who + "batch meshes need 64 <= nx, ny <= 1024, multiples of 8");
         if (!make_kparams(p, &b->kp[s], &why)) return give_up(LBM_E_INVALID, who + why);
+        // each row's populations side by side, as in a context
+        set_state_layout(&b->kp[s], true);
         if (!b->kp[s].use_iir_rows) return give_up(LBM_E_INVALID, who + "row pass shape");
         if (p->collision != params[0].collision)
             return give_up(LBM_E_INVALID, who + "every simulation of a batch needs the same collision");
@@ -1522,8 +1524,13 @@ lbm_status lbm_batch_get_state(lbm_batch *b, int32_t sim, double *f)
     lbm_status st = benter(b);
     if (st != LBM_OK) return st;
     if (sim < 0 || sim >= b->n || !f) return bfail(b, LBM_E_INVALID, "no such simulation");
-    BHIP_OR(b, hipMemcpyAsync(f, b->sb[sim].f[sim_parity(b, sim)], 9 * b->N[sim] * sizeof(double),
-                              hipMemcpyDeviceToHost, b->stream));
+    // into planes f[9][ny][nx], one strided copy per population
+    const KParams &k = b->kp[sim];
+    const size_t nx = k.nx, N = b->N[sim], row = nx * sizeof(double);
+    const double *src = b->sb[sim].f[sim_parity(b, sim)];
+    for (int q = 0; q < 9; ++q)
+        BHIP_OR(b, hipMemcpy2DAsync(f + q * N, row, src + q * k.fq, k.fr * sizeof(double), row,
+                                    (size_t)k.ny, hipMemcpyDeviceToHost, b->stream));
     BHIP_OR(b, hipStreamSynchronize(b->stream));
     return LBM_OK;
 }
