@@ -183,10 +183,15 @@ def sweep_bench(lbm, inputs, which):
 # 512^2) runs BF16 inference only and leaves out the tanh start with the
 # fluid at rest, to stay within minutes; its warm start uses the network
 # within 80 nodes of the interface (the 256^2 training meshes reach about
-# 125 nodes from their drops) and the Maxwell gas at rest beyond 90.
+# 125 nodes from their drops) and the Maxwell gas at rest beyond 90.  The
+# "full512" set trains on 64 drops of the same radii on 512^2 meshes (the
+# evaluation's size, whose gas far field the network then sees) and uses the
+# network everywhere on the same 32 unseen drops.
 WARM = {"small": dict(wl="pr", train=96, train_n=128, eval=8, eval_n=128),
         "full": dict(wl="pr", train=192, train_n=256, eval=32, eval_n=512, modes=(True,),
                      at_rest=False, reach=80.0),
+        "full512": dict(wl="pr", train=64, train_n=512, train_r_scale=0.5, eval=32, eval_n=512,
+                        eval_r_scale=0.5, modes=(True,), at_rest=False),
         "cs-small": dict(wl="cs", train=96, train_n=128, eval=8, eval_n=128),
         "cs-full": dict(wl="cs", train=192, train_n=256, eval=32, eval_n=512)}
 
@@ -198,14 +203,16 @@ def warmstart_bench(which):
     log("warm start %s: converging %d training drops at %d^2" % (which, cfg["train"],
                                                                cfg["train_n"]))
     x, t, info = warmstart.training_set(5, cfg["train"], cfg["train_n"], 1e-12, 100, 1_000_000,
-                                        log=log, wl=cfg["wl"])
+                                        log=log, wl=cfg["wl"],
+                                        r_scale=cfg.get("train_r_scale", 1.0))
     net, losses, secs = warmstart.train_network(x, t)
     log("  trained in %.1f s (final loss %.3e)" % (secs, float(losses[-20:].mean())))
     # radii of the unseen drops drawn from the training drops' range
     # BF16 inference (the network's deployed precision) and FP32 beside it
     res = warmstart.compare(net, 55, cfg["eval"], cfg["eval_n"], 1e-12, 100, 3_000_000, log=log,
                             modes=cfg.get("modes", (True, False)),
-                            r_scale=cfg["train_n"] / cfg["eval_n"], wl=cfg["wl"],
+                            r_scale=cfg.get("eval_r_scale", cfg["train_n"] / cfg["eval_n"]),
+                            wl=cfg["wl"],
                             at_rest=cfg.get("at_rest", True),
                             reach=cfg.get("reach", math.inf))
     net.close()
@@ -234,7 +241,8 @@ def warmstart_bench(which):
         "set": which, "workload": cfg["wl"], "training": info, "samples": int(len(t)),
         "train_s": round(secs, 2),
         "eval_drops": cfg["eval"], "eval_n": cfg["eval_n"],
-        "eval_radius_range": [round(rr[r] * cfg["train_n"], 1) for r in ("r_lo", "r_hi")],
+        "eval_radius_range": [round(rr[r] * cfg["train_n"] * cfg.get("train_r_scale", 1.0), 1)
+                              for r in ("r_lo", "r_hi")],
         "tol": 1e-12, "check_every": 100,
         "inference": res["inference"],
         "reach": None if math.isinf(res["reach"]) else res["reach"],  # None: everywhere

@@ -130,12 +130,14 @@ def samples(member, p, radius, rho, ux, uy, stride=2, wl="cs"):
     return features(member, radius, d, th, wl), t.astype(np.float32)
 
 
-def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2, wl="cs"):
+def training_set(seed, count, n, tol, every, max_steps, log=None, stride=2, wl="cs",
+                 r_scale=1.0):
     """Converge `count` drops of workload `wl` at n x n from the tanh start
-    and return (x, t, info)."""
+    and return (x, t, info).  r_scale scales the drawn radii (drops of the
+    size a smaller mesh holds, on a mesh as large as the evaluation's)."""
     ms = members(seed, count, wl)
     plist = [drop_params(m, n, wl) for m in ms]
-    radii = [m["r_frac"] * n for m in ms]
+    radii = [r_scale * m["r_frac"] * n for m in ms]
     b, steps, sts, secs = converge(plist, [tanh_start(p, R, wl) for p, R in zip(plist, radii)],
                                    tol, every, max_steps, log)
     xs, ts = [], []
