@@ -920,6 +920,19 @@ __device__ __forceinline__ void rows_collide_body(
                  gb = (size_t)y * p.gr + x0;
     constexpr int NI = KEEP ? 9 : 1;
     double fi[NI][LC], rho[LC], mv[LC], jx[LC], jy[LC];
+    // a segment's loads that do not depend on f (the rho and mu planes over
+    // its window, F_y) go out first, so that their latency hides behind the
+    // populations' (they are used after the moment sums and the solves'
+    // barriers); over whole rows, where the rows' data are cache-resident on
+    // the meshes that use them, they follow the populations
+    double Fy[LC], wr[LC], wu[LC];
+    if (SEG) {
+        if ((int)threadIdx.x < nw) {
+            vload<LC>(rho_in + base, wr);
+            vload<LC>(mu + base, wu);
+        }
+        if (m.ok) vload<LC>(fy + base, Fy);
+    }
     if (m.ok) {
         // rho = f0 + f1 + ... + f8 in index order; momentum in opposite pairs,
         // jx = (f1 - f3) + (f5 - f6) + (f8 - f7), jy = (f2 - f4) + (f5 - f8) +
@@ -951,23 +964,18 @@ __device__ __forceinline__ void rows_collide_body(
         }
         if (!SEG) vload<LC>(mu + base, mv);
     }
-    double Fy[LC], Fx[LC];
+    double Fx[LC];
     if (SEG) {
         // F_x of Eq. 12 (or of the pseudopotential model) from the planes,
         // bitwise as a whole-row derivative pass over them would give it
         const int w = threadIdx.x;
-        double r[LC], u[LC], dxr[LC], dxm[LC];
-        if (w < nw) {
-            vload<LC>(rho_in + base, r);
-            vload<LC>(mu + base, u);
-        }
-        if (!p.sc) iir_solve_window<LC>(p, w, nw, p.iir_qL_row, r, L.vbuf, L.cP, L.cB, dxr);
-        iir_solve_window<LC>(p, w, nw, p.iir_qL_row, u, L.vbuf, L.cP, L.cB, dxm);
+        double dxr[LC], dxm[LC];
+        if (!p.sc) iir_solve_window<LC>(p, w, nw, p.iir_qL_row, wr, L.vbuf, L.cP, L.cB, dxr);
+        iir_solve_window<LC>(p, w, nw, p.iir_qL_row, wu, L.vbuf, L.cP, L.cB, dxm);
         if (m.ok) {
-            vload<LC>(fy + base, Fy);
 #pragma unroll
             for (int k = 0; k < LC; ++k)
-                Fx[k] = p.sc ? CS2 * u[k] * dxm[k] : -r[k] * dxm[k] + CS2 * dxr[k];
+                Fx[k] = p.sc ? CS2 * wu[k] * dxm[k] : -wr[k] * dxm[k] + CS2 * dxr[k];
         }
     } else {
         // F_x of Eq. 12, or of the pseudopotential model (mv holds psi)
