@@ -622,7 +622,10 @@ struct StreamLds {
     static constexpr int NE = ST + MC + 2;  // edge slots: see stream_solve
     static_assert(ST > MC, "the next tile must hold the chunks whose carries a tile sums");
     static_assert((R & (R - 1)) == 0, "the carry ring is indexed with a mask");
-    static constexpr int doubles = NE * 4 * SW + 3 * R * SW + (ST + MC) * SW + 3 * 4 * SW + MC * SW;
+    // edges, three carry rings, anti-causal carries, the left buffers of the
+    // three solves, and the look-ahead chunks' causal carries
+    static constexpr int doubles =
+        NE * 4 * SW + 3 * R * SW + (ST + MC) * SW + 3 * 4 * SW + MC * SW;
 };
 
 // Solve k (0, 1, 2) of step s: the derivative d of the thread's chunk of the
@@ -823,14 +826,15 @@ __global__ __launch_bounds__(SW * ST) void k_cols_mu_stream(KParams p,
 #pragma unroll
                 for (int k = 0; k < LC; ++k) d2[k] = 0.0;
             }
+            // (wetting walls: the solve differentiates mu - mu_wall, odd
+            // about the walls; no chunk lies beyond a wall here)
             const int v2 = (s - 2) * ST + c, y2 = (v2 - E) * LC;
-            const double sg = (p.bc_y && (y2 < 0 || y2 >= ny)) ? -1.0 : 1.0;
             double m[LC];
 #pragma unroll
             for (int k = 0; k < LC; ++k) {
                 m[k] = mx[k];
                 if (!p.kappa_zero) m[k] -= p.kappa * d2[k];
-                mw[k] = p.wet ? sg * (m[k] - p.mu_wall) : m[k];
+                mw[k] = p.wet ? m[k] - p.mu_wall : m[k];
             }
             if (v2 >= E && v2 < E + nc) {
                 double *q = mu_out + (ptrdiff_t)y2 * nx + col;
@@ -1510,12 +1514,15 @@ int col_stream_chunk(int ny) { return ny % 8 == 0 ? 8 : 4; }
 size_t col_stream_lds(int width, int lc)
 {
     int d = 0;
-    if (lc == 8)
-        d = width == 8 ? StreamLds<8, 64, 8>::doubles
-                       : (width == 32 ? StreamLds<32, 16, 8>::doubles : StreamLds<16, 32, 8>::doubles);
-    else
-        d = width == 8 ? StreamLds<8, 64, 4>::doubles
-                       : (width == 32 ? StreamLds<32, 16, 4>::doubles : StreamLds<16, 32, 4>::doubles);
+    if (lc == 8) {
+        d = width == 8    ? StreamLds<8, 64, 8>::doubles
+            : width == 32 ? StreamLds<32, 16, 8>::doubles
+                          : StreamLds<16, 32, 8>::doubles;
+    } else {
+        d = width == 8    ? StreamLds<8, 64, 4>::doubles
+            : width == 32 ? StreamLds<32, 16, 4>::doubles
+                          : StreamLds<16, 32, 4>::doubles;
+    }
     return sizeof(double) * (size_t)d;
 }
 
