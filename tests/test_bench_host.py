@@ -32,6 +32,26 @@ def test_strict_json_replaces_non_finite_numbers():
                    "f": "x", "g": [3.0]}
 
 
+def test_column_shape_reports_the_fastest_column_candidate():
+    """The autotuner's table mixes column shapes (width > 0) and collision
+    variants (width 0); the reported column shape is the fastest of the
+    former, whatever the latter's times."""
+    table = {(4, 8): 0.61, (16, lbm.COLUMN_STREAM): 0.55, (8, -8): 0.60, (0, 2): 0.45,
+             (0, 0): 0.56}
+    assert bench.column_shape(table) == [16, lbm.COLUMN_STREAM]
+    table[(4, 16)] = 0.50
+    assert bench.column_shape(table) == [4, 16]
+
+
+def test_warm_start_sets_scale_the_radii_consistently():
+    """The 512^2-trained set draws training and unseen drops of the same
+    absolute radii (those of the 256^2-trained full set's unseen drops)."""
+    full, f512 = bench.WARM["full"], bench.WARM["full512"]
+    eval_scale_full = full["train_n"] / full["eval_n"]
+    assert f512["eval_n"] == full["eval_n"] and f512["eval_r_scale"] == eval_scale_full
+    assert f512["train_n"] * f512["train_r_scale"] == full["train_n"]
+
+
 def test_warm_start_entry_compares_drops_that_converged_from_both(monkeypatch):
     bad = lbm.LBM_E_NONFINITE
 
