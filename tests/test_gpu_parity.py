@@ -97,15 +97,23 @@ def test_ragged_tiles_pr_drop_with_limit():
 
 
 @pytest.mark.parametrize("walls", [0, 1])
-def test_general_reduction_path(walls):
-    """98 x 66: lines of >= 64 nodes that are not multiples of 4 take the
-    general parallel-cyclic-reduction kernels in both directions."""
-    nx, ny = 98, 66
+@pytest.mark.parametrize("nx,ny", [(98, 66), (99, 67)])
+def test_general_reduction_path(walls, nx, ny):
+    """98 x 66 and 99 x 67: lines of >= 64 nodes that are not multiples of 4
+    take the general parallel-cyclic-reduction kernels in both directions
+    (odd rows: each row's nine populations side by side in an odd number of
+    doubles per population; the state copied out and back bit for bit)."""
     p, op = _case_params(lbm.EOS_PR, 0.6, nx, ny, kappa=0.002, tau=0.8, k=0.1, mu_cap=6.0,
                          bc_y=walls)
     g, l = A.coexistence(p.eos, p.T_r)
     rho0, ux0, uy0 = inputs.droplet(nx, ny, g, l, 18.0, 5.0, seed=11, noise=1e-6)
-    _run_case("general98x66-walls%d" % walls, p, op, rho0, ux0, uy0, [50, 200])
+    _run_case("general%dx%d-walls%d" % (nx, ny, walls), p, op, rho0, ux0, uy0, [50, 200])
+    s = lbm.Solver(p, rho0, ux0, uy0)
+    s.step(10)
+    f = s.get_state()
+    s.set_state(f)
+    np.testing.assert_array_equal(s.get_state(), f)
+    s.close()
 
 
 @pytest.mark.parametrize("walls,nx,ny", [(0, 128, 256), (1, 128, 256), (1, 64, 2048)])
