@@ -626,6 +626,35 @@ def test_column_stream_full_size_splash(golden_dir):
     assert er <= TOL and ev <= TOL
 
 
+def test_large_mesh_column_shapes_agree():
+    """16384 x 8192 CS splash between walls (134 M nodes, the bench's large
+    mesh; rows over windowed segments): 20 steps with the column pass
+    streamed down 32-column strips (the autotuner's choice there) and over
+    4-column tiles with windows agree to round-off at every node."""
+    import torch
+    nx, ny = 16384, 8192
+    p = lbm.params(lbm.EOS_CS, 0.6, nx, ny, kappa=0.1, tau=0.6, k=0.2, mu_cap=6.0, bc_y=1)
+    g, l = A.coexistence(A.EOS_CS, 0.6)
+    print("\n[case] 16384x8192 splash, streamed columns against tiles", flush=True)
+    d = [torch.from_numpy(a).cuda() for a in
+         inputs.splash(nx, ny, g, l, 400.0, 5.0, film=160, drop_uy=-0.05)]
+    out = []
+    for shape in ((32, lbm.COLUMN_STREAM), (4, -8)):
+        s = lbm.Solver(p, *d)
+        s.set_column_shape(*shape)
+        s.step(20)
+        out.append(s.moments(device=True))
+        s.close()
+    del d
+    (r1, vx1, vy1), (r2, vx2, vy2) = out
+    er = ((r1 - r2).abs() / r2.abs()).max().item()
+    vmax = max(vx2.abs().max().item(), vy2.abs().max().item())
+    ev = max((vx1 - vx2).abs().max().item(), (vy1 - vy2).abs().max().item()) / vmax
+    print("  rel err rho %.2e, v %.2e" % (er, ev), flush=True)
+    assert bool(torch.isfinite(r1).all())
+    assert er <= 1e-12 and ev <= 1e-10
+
+
 @pytest.mark.parametrize("case", ["cs64", "pr300x200walls", "split3072x40"])
 def test_graph_replay_matches_launches(case):
     """Runs of steps replayed from captured HIP graphs (lbm_set_graph_steps)
